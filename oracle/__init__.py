@@ -1,0 +1,187 @@
+"""CPU oracle of the Flow Fields search (FlowFields++, Sec. 3.1).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The product path never imports it.
+
+``build()`` compiles ``ff_oracle.c`` into ``libff_oracle.so`` beside it; the
+functions below are thin ctypes/numpy wrappers with no arithmetic of their
+own.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ff_oracle.c")
+_LIB = os.path.join(_HERE, "libff_oracle.so")
+
+INF = 2**31 - 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99, -O2, single-threaded)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-shared", "-fPIC",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("seed_stride", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
+                ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_int16), ctypes.POINTER(ctypes.c_int32))
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        l = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i = ctypes.c_int
+        l.ffo_gray.argtypes = [P, i, i, i, P]
+        l.ffo_down2.argtypes = [P, i, i, P]
+        l.ffo_descriptors.argtypes = [P, i, i, P]
+        l.ffo_seed_nn.argtypes = [P, P, i, i, i, P]
+        l.ffo_philox4x32_10.argtypes = [P, P, P]
+        l.ffo_cost.argtypes = [P, P, i, i, i, i, i, i]
+        l.ffo_cost.restype = ctypes.c_int32
+        l.ffo_sweep.argtypes = [P, P, i, i, i, P, P]
+        l.ffo_random_search.argtypes = [P, P, i, i, i, i, i, i, ctypes.c_uint64, P, P]
+        l.ffo_match.argtypes = [ctypes.POINTER(Params), P, P, i, i, i, P, P, P, P, P, P,
+                                TRACE_FN, P]
+        l.ffo_match.restype = ctypes.c_int
+        _lib = l
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED) -> Params:
+    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed)
+
+
+def gray(img: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape[:2]
+    C = 1 if img.ndim == 2 else img.shape[2]
+    out = np.empty((H, W), np.uint8)
+    lib().ffo_gray(_p(img), W, H, C, _p(out))
+    return out
+
+
+def down2(plane: np.ndarray) -> np.ndarray:
+    plane = np.ascontiguousarray(plane, dtype=np.uint8)
+    H, W = plane.shape
+    out = np.empty((H >> 1, W >> 1), np.uint8)
+    lib().ffo_down2(_p(plane), W, H, _p(out))
+    return out
+
+
+def pyramid(gray_plane: np.ndarray, levels: int) -> list:
+    out = [np.ascontiguousarray(gray_plane, dtype=np.uint8)]
+    for _ in range(1, levels):
+        out.append(down2(out[-1]))
+    return out
+
+
+def descriptors(plane: np.ndarray) -> np.ndarray:
+    plane = np.ascontiguousarray(plane, dtype=np.uint8)
+    H, W = plane.shape
+    out = np.empty((H, W, 16), np.int8)
+    lib().ffo_descriptors(_p(plane), W, H, _p(out))
+    return out
+
+
+def seed_nn(DA: np.ndarray, DB: np.ndarray, stride: int) -> np.ndarray:
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    nsx, nsy = -(-W // stride), -(-H // stride)
+    out = np.empty((nsy, nsx), np.int32)
+    lib().ffo_seed_nn(_p(DA), _p(DB), W, H, stride, _p(out))
+    return out
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().ffo_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def cost(DA, DB, x, y, fx, fy) -> int:
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    return int(lib().ffo_cost(_p(DA), _p(DB), W, H, x, y, fx, fy))
+
+
+def sweep(DA, DB, flow, cst, dir_code: int):
+    """In-place copy semantics: returns new (flow, cost) after one sweep."""
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_sweep(_p(DA), _p(DB), W, H, dir_code, _p(f), _p(c))
+    return f, c
+
+
+def random_search(DA, DB, flow, cst, level, it, pss, radius, seed):
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_random_search(_p(DA), _p(DB), W, H, level, it, pss, radius,
+                            ctypes.c_uint64(seed), _p(f), _p(c))
+    return f, c
+
+
+def match(img1: np.ndarray, img2: np.ndarray, prm: Params | None = None, trace=None):
+    """Run the whole search.  Returns dict with flow_f/cost_f/mask_f and the
+    backward outputs.  ``trace(dir, level, iter, stage, flow, cost)`` is
+    called with copies of the state after every stage when given."""
+    prm = prm or params()
+    img1 = np.ascontiguousarray(img1, dtype=np.uint8)
+    img2 = np.ascontiguousarray(img2, dtype=np.uint8)
+    assert img1.shape == img2.shape
+    H, W = img1.shape[:2]
+    C = 1 if img1.ndim == 2 else img1.shape[2]
+    out = {
+        "flow_f": np.empty((H, W, 2), np.int16), "cost_f": np.empty((H, W), np.int32),
+        "mask_f": np.empty((H, W), np.uint8), "flow_b": np.empty((H, W, 2), np.int16),
+        "cost_b": np.empty((H, W), np.int32), "mask_b": np.empty((H, W), np.uint8),
+    }
+    if trace is not None:
+        def _cb(user, d, l, t, s, w, h, fp, cp):
+            f = np.ctypeslib.as_array(fp, shape=(h, w, 2)).copy()
+            c = np.ctypeslib.as_array(cp, shape=(h, w)).copy()
+            trace(d, l, t, s, f, c)
+        cb = TRACE_FN(_cb)
+    else:
+        cb = TRACE_FN()
+    rc = lib().ffo_match(ctypes.byref(prm), _p(img1), _p(img2), W, H, C,
+                         _p(out["flow_f"]), _p(out["cost_f"]), _p(out["mask_f"]),
+                         _p(out["flow_b"]), _p(out["cost_b"]), _p(out["mask_b"]), cb, None)
+    if rc != 0:
+        raise ValueError("oracle rejected the input")
+    return out

@@ -1,0 +1,76 @@
+/*
+ * ff_oracle.h -- CPU oracle of the Flow Fields dense correspondence search
+ * (FlowFields++, Sec. 3.1 "Matches"): descriptors, seed initialisation at the
+ * lowest resolution, coarse-to-fine propagation with random search, and the
+ * forward-backward consistency check.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded reference
+ * used by the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark.  The product path (the HIP library) never links, loads or calls
+ * it, and it shares no code, header or table with that library.
+ *
+ * All arithmetic is integer; every output is defined exactly, so the HIP path
+ * must reproduce it bit for bit.
+ */
+#ifndef FF_ORACLE_H
+#define FF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFO_INF INT32_MAX
+#define FFO_K   16          /* descriptor length */
+
+typedef struct {
+    int32_t  levels;        /* pyramid levels L >= 1                         */
+    int32_t  seed_stride;   /* seed grid step at the coarsest level (3)      */
+    int32_t  iters;         /* propagation iterations T per level (2)        */
+    int32_t  rs_radius;     /* random-search radius R (16): R, R>>1, ..., 1   */
+    int32_t  fb_eps;        /* consistency threshold epsilon in px (1)       */
+    uint64_t seed;          /* random-search key                             */
+} ffo_params;
+
+/* Trace hook: called after every stage with the direction's state.
+ * stage: 0 = level init, 1 = LR, 2 = RL, 3 = RS0, 4 = TB, 5 = RS1, 6 = BT,
+ * 7 = RS2.  flow is [H][W][2] int16 (dx, dy), cost is [H][W] int32.        */
+typedef void (*ffo_trace_fn)(void* user, int dir, int level, int iter, int stage,
+                             int W, int H, const int16_t* flow, const int32_t* cost);
+
+/* Sec. 3.1 input: colour to gray, Y = (77 R + 150 G + 29 B + 128) >> 8.  */
+void ffo_gray(const uint8_t* img, int W, int H, int C, uint8_t* gray);
+/* One 2x2 box-filter pyramid step, rounding half up, floor dimensions.  */
+void ffo_down2(const uint8_t* src, int W, int H, uint8_t* dst);
+/* 16 Walsh-Hadamard coefficients of the 8x8 patch at every pixel, int8.  */
+void ffo_descriptors(const uint8_t* P, int W, int H, int8_t* D);
+/* Exact nearest neighbour of every seed (stride grid) of A among all pixels
+ * of B, squared L2 over the descriptors, ties to the lowest linear index.
+ * idx has ceil(H/stride) * ceil(W/stride) entries, seed-row-major.       */
+void ffo_seed_nn(const int8_t* DA, const int8_t* DB, int W, int H, int stride, int32_t* idx);
+/* Philox4x32 with 10 rounds (Salmon et al., SC'11).                        */
+void ffo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Matching cost: SAD of the two descriptors, INF when p+f leaves image B.  */
+int32_t ffo_cost(const int8_t* DA, const int8_t* DB, int W, int H, int x, int y, int fx, int fy);
+/* One directional sweep over the whole state of one level.
+ * dir_code: 0 = LR, 1 = RL, 2 = TB, 3 = BT.  flow/cost updated in place.   */
+void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
+               int16_t* flow, int32_t* cost);
+/* One random-search pass over every pixel of one level.                    */
+void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int level,
+                       int iter, int pass, int radius, uint64_t seed,
+                       int16_t* flow, int32_t* cost);
+
+/* Full search for one pair.  img1/img2 are [H][W][C] uint8, C in {1, 3}.
+ * flow_* [H][W][2] int16, cost_* [H][W] int32, mask_* [H][W] uint8.
+ * The backward outputs may be NULL.  Returns 0, or -1 on invalid input.   */
+int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
+              int W, int H, int C,
+              int16_t* flow_f, int32_t* cost_f, uint8_t* mask_f,
+              int16_t* flow_b, int32_t* cost_b, uint8_t* mask_b,
+              ffo_trace_fn trace, void* user);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
