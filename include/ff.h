@@ -1,0 +1,152 @@
+/*
+ * ff.h -- C ABI of the MI355X (gfx950) Flow Fields dense correspondence search.
+ *
+ * The search is the matching stage of FlowFields++ (Sec. 3.1 "Matches"):
+ * feature descriptors, initial matches at the lowest pyramid resolution,
+ * propagation into all four directions with random search at every scale
+ * of a coarse-to-fine pyramid, and the forward-backward consistency check
+ * with threshold epsilon (Sec. 3.1; Table 3).  Every output is integer and
+ * exactly defined:
+ *   - luma Y = (77 R + 150 G + 29 B + 128) >> 8 (C = 3) or the input (C = 1);
+ *   - pyramid: 2x2 box mean rounded half up, floor dimensions;
+ *   - descriptors: the 16 lowest-sequency 2-D Walsh-Hadamard coefficients of
+ *     the 8x8 patch (offsets -3..+4, replicated border), floor(c / 64), DC
+ *     shifted by -128, as int8;
+ *   - cost: SAD of two descriptors; INT32_MAX when the target leaves image B;
+ *   - seeds: exact nearest neighbour (squared L2, lowest linear index on
+ *     ties) of every stride-grid pixel at the coarsest level among all pixels;
+ *   - per level: init (seed of the pixel's stride cell, or twice the parent
+ *     flow), then `iters` times: LR, RL sweeps, random search 0, TB sweep,
+ *     random search 1, BT sweep, random search 2;
+ *   - random search: radii R, R>>1, ..., 1 around the pre-pass flow, offsets
+ *     from Philox4x32-10 at counter (y*W+x, level, iter<<2|pass, j>>1) and
+ *     key (seed low, seed high), accepted on a strictly lower cost;
+ *   - mask(p) = 1 iff both matches are valid and |F(p) + B(p + F(p))|^2 <= eps^2.
+ *
+ * Memory: every pointer in ff_pair is DEVICE memory owned by the caller.
+ * The handle owns its workspaces (pyramids, descriptors, search state, seed
+ * tables), allocated on first use for a shape/batch and reused after.
+ * Calls are stream-ordered: they validate synchronously, enqueue the work on
+ * `stream` (a hipStream_t, or NULL for the null stream) and return; outputs
+ * are valid once the stream reaches that point.  A handle must not be used
+ * from two threads at once.  Errors of already-enqueued work surface as
+ * FF_ERR_HIP on a later call.
+ */
+#ifndef FF_H
+#define FF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ff_ctx* ff_handle;
+
+typedef enum {
+    FF_OK = 0,
+    FF_ERR_INVALID = 1,      /* bad argument: NULL pointer, size, parameter  */
+    FF_ERR_OOM = 2,          /* device allocation failed                    */
+    FF_ERR_BUDGET = 3,       /* workspace would exceed params.hbm_budget     */
+    FF_ERR_HIP = 4,          /* a HIP runtime call failed (see ff_last_error) */
+    FF_ERR_UNSUPPORTED = 5,  /* device is not gfx950                         */
+    FF_ERR_BUSY = 6          /* serving queue full                           */
+} ff_status;
+
+/* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 for KITTI). */
+typedef struct {
+    int32_t  levels;        /* pyramid levels L, 1..8 (3 or 4 in the workloads)  */
+    int32_t  seed_stride;   /* seed grid step at the coarsest level (3)          */
+    int32_t  iters;         /* iterations per level (2)                          */
+    int32_t  rs_radius;     /* random-search radius R, 0..1024 (16)              */
+    int32_t  fb_eps;        /* consistency threshold in px, 0..1024 (1)          */
+    uint64_t seed;          /* random-search key                                 */
+    uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
+    uint32_t flags;         /* reserved, must be 0                               */
+} ff_params;
+
+/* One image pair and its outputs.  Both frames are [H][W][C] uint8,
+ * row pitch W*C bytes, C in {1, 3}; 1 <= W, H <= 8192 and
+ * min(W, H) >> (levels-1) >= 1.
+ * flow_*: [H][W][2] int16 (dx, dy); cost_*: [H][W] int32 (INT32_MAX =
+ * no valid match); mask_*: [H][W] uint8 (1 = consistent).  flow_fwd and
+ * mask_fwd are required; every other output may be NULL.                 */
+typedef struct {
+    const uint8_t* img1;
+    const uint8_t* img2;
+    int32_t width, height, channels;
+    int16_t* flow_fwd;
+    int32_t* cost_fwd;
+    uint8_t* mask_fwd;
+    int16_t* flow_bwd;
+    int32_t* cost_bwd;
+    uint8_t* mask_bwd;
+} ff_pair;
+
+/* Create a handle on HIP device `device` (must be gfx950).  Copies *params. */
+ff_status ff_create(const ff_params* params, int device, ff_handle* out);
+
+/* Match one pair (the whole search above) on `stream`. */
+ff_status ff_match_pair(ff_handle h, const ff_pair* pair, void* stream);
+
+/* Match n independent pairs, of any sizes, in one grouped pass: every stage
+ * runs once over all pairs.  Outputs are bit-identical to n calls of
+ * ff_match_pair.  n >= 1. */
+ff_status ff_match_batch(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
+
+/* Synchronise the handle's device and free everything it owns. */
+void ff_destroy(ff_handle h);
+
+/* Message of the last non-OK status on this handle (static string when h is
+ * NULL).  Valid until the next call on the handle. */
+const char* ff_last_error(ff_handle h);
+
+/* Bytes of device workspace a batch of these pairs needs (no allocation). */
+uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
+
+/* ---- per-kernel timing (tracing) ------------------------------------------
+ * When enabled, every launch the handle enqueues is bracketed by a pair of
+ * HIP events on the launch stream.  ff_profile_read synchronises those
+ * events, writes one entry per kernel (launch count and summed device time
+ * between its events) into out[0..max), returns the number of entries, and
+ * clears the record.  Names: gray, down2, desc, seed_records, seed_nn, init,
+ * row_phase, col_phase, fb.  Returns -1 on error.                           */
+typedef struct {
+    char    name[32];
+    int32_t launches;
+    double  total_ms;
+} ff_profile_entry;
+
+ff_status ff_profile_enable(ff_handle h, int32_t on);
+int32_t   ff_profile_read(ff_handle h, ff_profile_entry* out, int32_t max);
+
+/* ---- intermediates, for parity tests against an independent CPU model ---- */
+typedef enum {
+    FF_STAGE_GRAY = 0,      /* image `image` level-0 luma: [H][W] uint8               */
+    FF_STAGE_PYRAMID = 1,   /* image `image` level `level`: [H_l][W_l] uint8          */
+    FF_STAGE_DESC = 2,      /* image `image` level `level`: [H_l][W_l][16] int8       */
+    FF_STAGE_SEEDS = 3,     /* direction `dir`: seed-grid NN index, [nsy][nsx] int32  */
+    FF_STAGE_STATE = 4      /* direction `dir`, level, iter, step: [H_l][W_l] of
+                               {int16 dx, int16 dy, int32 cost}; step 0 = after init
+                               (iter ignored), 1 LR, 2 RL, 3 RS0, 4 TB, 5 RS1, 6 BT,
+                               7 RS2                                                 */
+} ff_stage_kind;
+
+typedef struct {
+    int32_t kind;           /* ff_stage_kind                     */
+    int32_t image;          /* 0 = img1, 1 = img2 (GRAY/PYRAMID/DESC) */
+    int32_t dir;            /* 0 = forward, 1 = backward (SEEDS/STATE) */
+    int32_t level;
+    int32_t iter;
+    int32_t step;
+} ff_stage;
+
+/* Run the search of one pair up to the named point and copy that
+ * intermediate into `dst` (device memory of the size stated above). */
+ff_status ff_debug_stage(ff_handle h, const ff_pair* pair, const ff_stage* which,
+                         void* dst, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FF_H */

@@ -1,0 +1,52 @@
+// ff_internal.h -- device-side layout of one batch, shared by the HIP kernels
+// and the host runtime of libff (nothing outside libff includes it).
+//
+// HBM layout per pair (all buffers 256-byte aligned, carved from one arena):
+//   gray[l][i]   uint8  [H_l][W_l]        pyramid level l of image i
+//   desc[l][i]   uint8  [H_l][W_l][16]    descriptors, stored biased (d + 128)
+//                                         so the SAD unit works on unsigned bytes
+//   state[l][d]  int2   [H_l][W_l]        search state of direction d:
+//                                         .x = flow (int16 dx | int16 dy << 16),
+//                                         .y = cost (INT32_MAX = invalid)
+//   dbrec[i]     int8   [N][64]           seed-search database records of image i
+//                                         at the coarsest level (see k_seed_records)
+//   keys[d]      uint64 [nsy][nsx]        packed (score, ~index) of the best seed match
+#pragma once
+#include <stdint.h>
+
+namespace ff {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxSide = 8192;
+constexpr int32_t kInf = 0x7FFFFFFF;
+
+struct LevelDev {
+    int W, H;
+    uint8_t* gray[2];
+    uint8_t* desc[2];
+    int2* state[2];
+};
+
+struct PairDev {
+    const uint8_t* img[2];
+    int C;
+    int nsx, nsy;                    // seed grid at the coarsest level
+    LevelDev lv[kMaxLevels];
+    int8_t* dbrec[2];
+    unsigned long long* keys[2];
+    int16_t* flow[2];                // outputs (fwd, bwd); bwd entries may be null
+    int32_t* cost[2];
+    uint8_t* mask[2];
+};
+
+struct SearchConst {
+    int levels;
+    int stride;
+    int iters;
+    int radius;
+    int trials;                      // floor(log2 radius) + 1, 0 when radius == 0
+    int eps2;
+    uint32_t key0, key1;             // Philox key words
+};
+
+}  // namespace ff

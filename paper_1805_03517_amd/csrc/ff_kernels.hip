@@ -1,0 +1,673 @@
+// ff_kernels.hip -- gfx950 kernels of the Flow Fields search (FlowFields++,
+// Sec. 3.1 "Matches").  Every kernel is grouped over a batch: blockIdx.y (or
+// .z) selects the pair and the image or direction, the other grid axes cover
+// the largest level of the batch and blocks beyond a pair's own size exit.
+//
+// All arithmetic is integer and follows the schedule stated in include/ff.h;
+// the parallel forms used here (windowed relaxation of the scanline sweeps,
+// all random-search trials gathered before the sequential selection, MFMA
+// scoring of the seed search) reproduce that schedule's result exactly.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ff_internal.h"
+
+namespace ff {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ helpers ---
+__device__ __forceinline__ uint32_t pack_flow(int fx, int fy)
+{
+    return (uint32_t)(uint16_t)fx | ((uint32_t)(uint16_t)fy << 16);
+}
+__device__ __forceinline__ int flow_x(uint32_t f) { return (int)(int16_t)(f & 0xFFFFu); }
+__device__ __forceinline__ int flow_y(uint32_t f) { return (int)(int16_t)(f >> 16); }
+
+// SAD of two 16-byte descriptors held biased (unsigned) -- four v_sad_u8.
+__device__ __forceinline__ int32_t sad16(uint4 a, uint4 b)
+{
+    uint32_t s = __builtin_amdgcn_sad_u8(a.x, b.x, 0u);
+    s = __builtin_amdgcn_sad_u8(a.y, b.y, s);
+    s = __builtin_amdgcn_sad_u8(a.z, b.z, s);
+    s = __builtin_amdgcn_sad_u8(a.w, b.w, s);
+    return (int32_t)s;
+}
+
+// Matching cost of pixel (x, y) of A under flow f against descriptor plane
+// DB (Sec. 3.1: a distance of feature descriptors).  INF when the target
+// leaves the image; no load is issued then.
+__device__ __forceinline__ int32_t cost_at(const uint8_t* __restrict__ DB, int W, int H, int x, int y,
+                                           uint32_t f, uint4 a)
+{
+    int qx = x + flow_x(f), qy = y + flow_y(f);
+    if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
+    uint4 b = *reinterpret_cast<const uint4*>(DB + ((size_t)qy * W + qx) * 16);
+    return sad16(a, b);
+}
+
+__device__ __forceinline__ uint4 load_desc(const uint8_t* __restrict__ D, size_t idx)
+{
+    return *reinterpret_cast<const uint4*>(D + idx * 16);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4-word S-P network,
+// key advanced by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Random search of one pixel (Sec. 3.1: a small random offset added to each
+// flow component).  Trials j = 0..J-1 with radius R >> j around the pre-pass
+// flow v0; offsets come from the Philox block at counter
+// (y*W + x, level, iter << 2 | pass, j >> 1), words (0,1) for even j and
+// (2,3) for odd j.  All trial costs are gathered first (independent loads),
+// then selected in trial order with a strict '<', which equals the
+// sequential rule because a trial equal to the running best costs the same.
+template <int RC>
+__device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a,
+                                              const uint8_t* __restrict__ DB, int W, int H, int x,
+                                              int y, uint32_t level, uint32_t ctr2,
+                                              const SearchConst& sc)
+{
+    const int R = RC > 0 ? RC : sc.radius;
+    const int J = RC > 0 ? (31 - __builtin_clz((unsigned)(RC > 0 ? RC : 1)) + 1) : sc.trials;
+    const int vx = flow_x(bf), vy = flow_y(bf);
+    const uint32_t ctr0 = (uint32_t)(y * W + x);
+    if constexpr (RC > 0) {
+        constexpr int JC = 31 - __builtin_clz((unsigned)RC) + 1;
+        uint32_t cand[JC];
+        int32_t e[JC];
+        uint4 u = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < JC; ++j) {
+            if ((j & 1) == 0) u = philox4x32_10(make_uint4(ctr0, level, ctr2, (uint32_t)(j >> 1)), sc.key0, sc.key1);
+            const uint32_t ux = (j & 1) ? u.z : u.x;
+            const uint32_t uy = (j & 1) ? u.w : u.y;
+            const int r = RC >> j;
+            const uint32_t span = 2u * (uint32_t)r + 1u;
+            cand[j] = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
+            e[j] = cost_at(DB, W, H, x, y, cand[j], a);
+        }
+#pragma unroll
+        for (int j = 0; j < JC; ++j)
+            if (e[j] < bc) { bc = e[j]; bf = cand[j]; }
+        (void)R; (void)J;
+    } else {
+        uint4 u = make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < J; ++j) {
+            if ((j & 1) == 0) u = philox4x32_10(make_uint4(ctr0, level, ctr2, (uint32_t)(j >> 1)), sc.key0, sc.key1);
+            const uint32_t ux = (j & 1) ? u.z : u.x;
+            const uint32_t uy = (j & 1) ? u.w : u.y;
+            const int r = R >> j;
+            const uint32_t span = 2u * (uint32_t)r + 1u;
+            const uint32_t c = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
+            const int32_t ej = cost_at(DB, W, H, x, y, c, a);
+            if (ej < bc) { bc = ej; bf = c; }
+        }
+    }
+}
+
+// ------------------------------------------------------------- ingest ---
+// Level-0 luma of both images: Y = (77 R + 150 G + 29 B + 128) >> 8, C = 1
+// copies.  grid (pixels / 256, 2 * pairs).
+__global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int img = blockIdx.y & 1;
+    const int n = P.lv[0].W * P.lv[0].H;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint8_t* src = P.img[img];
+    uint8_t v;
+    if (P.C == 3) {
+        const uint8_t* p = src + (size_t)i * 3;
+        v = (uint8_t)((77u * p[0] + 150u * p[1] + 29u * p[2] + 128u) >> 8);
+    } else {
+        v = src[i];
+    }
+    P.lv[0].gray[img][i] = v;
+}
+
+// One pyramid step: 2x2 box mean rounded half up, floor dimensions.
+__global__ __launch_bounds__(256) void k_down2(const PairDev* __restrict__ pairs, int level)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int img = blockIdx.y & 1;
+    const LevelDev& S = P.lv[level - 1];
+    const LevelDev& D = P.lv[level];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= D.W * D.H) return;
+    const int x = i % D.W, y = i / D.W;
+    const uint8_t* s = S.gray[img] + (size_t)(2 * y) * S.W + 2 * x;
+    const uint32_t sum = (uint32_t)s[0] + s[1] + s[S.W] + s[S.W + 1];
+    D.gray[img][i] = (uint8_t)((sum + 2u) >> 2);
+}
+
+// -------------------------------------------------------- descriptors ---
+// 16 Walsh-Hadamard coefficients of the 8x8 patch at every pixel (Sec. 3.1),
+// separable: the four lowest-sequency Walsh functions on 8 samples are
+// constant on sample pairs, so a 1-D transform is 4 pair sums and one
+// 4-point butterfly.  A block covers 64 x 16 outputs; its 71 x 23 input
+// window (replicated border) and the 23 x 64 row transforms live in LDS.
+constexpr int kDescTX = 64, kDescTY = 16;
+
+__global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs, int level)
+{
+    const PairDev& P = pairs[blockIdx.z >> 1];
+    const int img = blockIdx.z & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, H = L.H;
+    const int x0 = blockIdx.x * kDescTX, y0 = blockIdx.y * kDescTY;
+    if (x0 >= W || y0 >= H) return;
+    __shared__ uint8_t tile[kDescTY + 7][kDescTX + 8];
+    __shared__ int16_t rowt[kDescTY + 7][kDescTX][4];
+    const uint8_t* src = L.gray[img];
+    for (int i = threadIdx.x; i < (kDescTY + 7) * (kDescTX + 7); i += 256) {
+        const int r = i / (kDescTX + 7), c = i % (kDescTX + 7);
+        const int gy = min(max(y0 - 3 + r, 0), H - 1);
+        const int gx = min(max(x0 - 3 + c, 0), W - 1);
+        tile[r][c] = src[(size_t)gy * W + gx];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (kDescTY + 7) * kDescTX; i += 256) {
+        const int r = i / kDescTX, c = i % kDescTX;
+        const int q0 = tile[r][c] + tile[r][c + 1], q1 = tile[r][c + 2] + tile[r][c + 3];
+        const int q2 = tile[r][c + 4] + tile[r][c + 5], q3 = tile[r][c + 6] + tile[r][c + 7];
+        rowt[r][c][0] = (int16_t)(q0 + q1 + q2 + q3);
+        rowt[r][c][1] = (int16_t)(q0 + q1 - q2 - q3);
+        rowt[r][c][2] = (int16_t)(q0 - q1 - q2 + q3);
+        rowt[r][c][3] = (int16_t)(q0 - q1 + q2 - q3);
+    }
+    __syncthreads();
+    uint8_t* dst = L.desc[img];
+    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {
+        const int c = i % kDescTX, r = i / kDescTX;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= W || y >= H) continue;
+        uint32_t words[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p0 = rowt[r][c][v] + rowt[r + 1][c][v], p1 = rowt[r + 2][c][v] + rowt[r + 3][c][v];
+            const int p2 = rowt[r + 4][c][v] + rowt[r + 5][c][v], p3 = rowt[r + 6][c][v] + rowt[r + 7][c][v];
+            const int cu[4] = {p0 + p1 + p2 + p3, p0 + p1 - p2 - p3, p0 - p1 - p2 + p3, p0 - p1 + p2 - p3};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 4 * u + v;
+                // floor(c / 64) as int8, DC shifted by -128; stored biased (+128)
+                const int d = (cu[u] >> 6) + (k == 0 ? 0 : 128);
+                words[k >> 2] |= (uint32_t)(d & 0xFF) << (8 * (k & 3));
+            }
+        }
+        *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = make_uint4(words[0], words[1], words[2], words[3]);
+    }
+}
+
+// ------------------------------------------------------------ seed NN ---
+// Database records for the exact seed search at the coarsest level.  The
+// score 2 a.b - |b|^2 (maximised; equivalent to minimising |a - b|^2) is one
+// v_mfma_i32_16x16x64_i8 per 16 x 16 tile: the 64-deep K axis holds
+//   A row  = [ a, a, g0, g1 ]      B column = [ b, b, beta0, beta1 ]
+// with constants g = (127 x 31, 1) and digits beta (31 in [-128, 0], the last
+// in [0, 126]) such that g . beta = -|b|^2 exactly.  Also clears the keys.
+__global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict__ pairs, int level)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int img = blockIdx.y & 1;
+    const LevelDev& L = P.lv[level];
+    const int N = L.W * L.H;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n < P.nsx * P.nsy) P.keys[img][n] = 0ull;
+    if (n >= N) return;
+    const uint4 db = load_desc(L.desc[img], n);
+    const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
+    const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+    int nb = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int v = (int)(int8_t)(bw[k >> 2] >> (8 * (k & 3)));
+        nb += v * v;
+    }
+    const int neg = -nb;                                        // in [-262144, 0]
+    const int X = -((-neg + 126) / 127);                        // floor(neg / 127), neg <= 0
+    const int rmd = neg - 127 * X;                              // 0..126
+    uint32_t beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int rem = X;
+#pragma unroll
+    for (int k = 0; k < 31; ++k) {
+        const int v = max(rem, -128);
+        rem -= v;
+        beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
+    }
+    beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
+    uint4* rec = reinterpret_cast<uint4*>(P.dbrec[img] + (size_t)n * 64);
+    rec[0] = b;
+    rec[1] = b;
+    rec[2] = make_uint4(beta[0], beta[1], beta[2], beta[3]);
+    rec[3] = make_uint4(beta[4], beta[5], beta[6], beta[7]);
+}
+
+// Exact nearest neighbour of every seed of A among all coarsest pixels of B
+// (Sec. 3.1 initial matches; the exact answer the kd-tree approximates).
+// A wave holds 16*MQ seeds as MFMA A operands and streams one split of the
+// database; per lane and seed row it keeps max((score << 11) | (2047 - t)),
+// so equal scores prefer the lower tile, then reduces over the 16 columns
+// preferring the lower column, and merges splits with a 64-bit atomicMax on
+// (score + 2^20) << 32 | ~index -- the lowest index wins every tie.
+// grid (ceil(seed tiles / 4), splits, 2 * pairs), 256 threads.
+template <int MQ>
+__global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pairs, int level,
+                                                int stride, int tiles_per_split)
+{
+    const PairDev& P = pairs[blockIdx.z >> 1];
+    const int dir = blockIdx.z & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int qbase = (blockIdx.x * 4 + wave) * 16 * MQ;
+    if (qbase >= Q) return;
+    const int ntiles = (N + 15) >> 4;
+    const int t0 = blockIdx.y * tiles_per_split;
+    if (t0 >= ntiles) return;
+    const int t1 = min(t0 + tiles_per_split, ntiles);
+    const int m = lane & 15, g = lane >> 4;
+
+    v4i A[MQ];
+#pragma unroll
+    for (int mq = 0; mq < MQ; ++mq) {
+        const int q = qbase + 16 * mq + m;
+        if (g >= 2) {
+            A[mq] = v4i{0x7F7F7F7F, 0x7F7F7F7F, 0x7F7F7F7F, g == 2 ? 0x7F7F7F7F : 0x017F7F7F};
+        } else if (q < Q) {
+            const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
+            const uint4 d = load_desc(L.desc[dir], (size_t)sy * W + sx);
+            A[mq] = v4i{(int)(d.x ^ 0x80808080u), (int)(d.y ^ 0x80808080u), (int)(d.z ^ 0x80808080u),
+                        (int)(d.w ^ 0x80808080u)};
+        } else {
+            A[mq] = v4i{0, 0, 0, 0};
+        }
+    }
+    int best[MQ][4];
+#pragma unroll
+    for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) best[mq][i] = INT32_MIN;
+
+    const v4i* rec = reinterpret_cast<const v4i*>(P.dbrec[dir ^ 1]);
+    for (int t = t0; t < t1; ++t) {
+        const int n = t * 16 + m;
+        const bool nvalid = n < N;
+        const v4i B = nvalid ? rec[(size_t)n * 4 + g] : v4i{0, 0, 0, 0};
+        const int tl = 2047 - (t - t0);
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq) {
+            const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, v4i{0, 0, 0, 0}, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | (uint32_t)tl) : INT32_MIN;
+                best[mq][i] = max(best[mq][i], key);
+            }
+        }
+    }
+#pragma unroll
+    for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int k = best[mq][i];
+            int j = m;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int ok = __shfl_xor(k, off, 64);
+                const int oj = __shfl_xor(j, off, 64);
+                if (ok > k || (ok == k && oj < j)) { k = ok; j = oj; }
+            }
+            const int q = qbase + 16 * mq + 4 * g + i;
+            if (m == 0 && q < Q && k != INT32_MIN) {
+                const int tloc = 2047 - (k & 2047);
+                const uint32_t n = (uint32_t)((t0 + tloc) * 16 + j);
+                const int score = k >> 11;
+                const unsigned long long key =
+                    ((unsigned long long)(uint32_t)(score + (1 << 20)) << 32) | (unsigned long long)(0xFFFFFFFFu - n);
+                atomicMax(&P.keys[dir][q], key);
+            }
+        }
+}
+
+// ----------------------------------------------------------- level init --
+// Coarsest level: every pixel takes the flow of the seed of its stride cell.
+// Finer levels: twice the flow of the parent pixel (clamped to the coarse
+// grid).  Cost re-evaluated.  grid (pixels / 256, 2 * pairs).
+__global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs, int level, int coarsest,
+                                              int stride)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, H = L.H;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= W * H) return;
+    const int x = i % W, y = i / W;
+    uint32_t f;
+    if (coarsest) {
+        const int si = x / stride, sj = y / stride;
+        const unsigned long long key = P.keys[dir][sj * P.nsx + si];
+        const uint32_t q = 0xFFFFFFFFu - (uint32_t)key;
+        f = pack_flow((int)(q % (uint32_t)W) - si * stride, (int)(q / (uint32_t)W) - sj * stride);
+    } else {
+        const LevelDev& C = P.lv[level + 1];
+        const int cx = min(x >> 1, C.W - 1), cy = min(y >> 1, C.H - 1);
+        const uint32_t cf = (uint32_t)C.state[dir][(size_t)cy * C.W + cx].x;
+        f = pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
+    }
+    const int32_t c = cost_at(L.desc[dir ^ 1], W, H, x, y, f, load_desc(L.desc[dir], i));
+    L.state[dir][i] = make_int2((int)f, c);
+}
+
+// ------------------------------------------------------------ row phase --
+// LR sweep, RL sweep and random-search pass 0 of one line per wave.
+// Sweep semantics (propagation, Sec. 3.1): scanning the line, a pixel takes
+// its predecessor's post-update flow iff that flow's cost is strictly lower
+// than the pixel's own pre-sweep cost.  The result is the unique solution h
+// of h_x = rule(pre_x, h_{x-1}); a 64-pixel chunk solves it by relaxation
+// (every lane re-applies the rule to its own pre-sweep value and its
+// neighbour's current value, DPP shift between lanes) until no lane's
+// neighbour value changes, with the chunk boundary value carried in.  The
+// count of rounds is one plus the longest propagation run in the chunk.
+// upto: 1 = LR only, 2 = LR + RL, 3 = LR + RL + RS0.
+// grid (ceil(H / 4), 2 * pairs), 256 threads (4 lines).
+template <int RC>
+__global__ __launch_bounds__(256) void k_row_phase(const PairDev* __restrict__ pairs, int level, int iter,
+                                                   int upto, SearchConst sc)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, H = L.H;
+    const int lane = threadIdx.x & 63;
+    const int y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y >= H) return;
+    const uint8_t* __restrict__ DA = L.desc[dir] + (size_t)y * W * 16;
+    const uint8_t* __restrict__ DB = L.desc[dir ^ 1];
+    int2* __restrict__ S = L.state[dir] + (size_t)y * W;
+
+    // ---- LR
+    uint32_t carry = 0;
+    for (int x0 = 0; x0 < W; x0 += 64) {
+        const int x = x0 + lane;
+        const bool valid = x < W;
+        const int2 s = valid ? S[x] : make_int2(0, kInf);
+        const uint4 a = valid ? load_desc(DA, x) : make_uint4(0, 0, 0, 0);
+        const uint32_t f0 = (uint32_t)s.x;
+        const int32_t c0 = s.y;
+        const bool has_pred = valid && x > 0;
+        uint32_t lp = f0, h = f0;
+        int32_t le = c0;
+        while (true) {
+            const uint32_t up = (uint32_t)__shfl_up((int)h, 1, 64);
+            const uint32_t pred = lane == 0 ? carry : up;
+            const bool need = has_pred && pred != lp;
+            if (!__any(need)) break;
+            if (need) {
+                lp = pred;
+                le = pred == f0 ? c0 : cost_at(DB, W, H, x, y, pred, a);
+            }
+            h = le < c0 ? lp : f0;
+        }
+        if (valid) S[x] = make_int2((int)h, le < c0 ? le : c0);
+        carry = (uint32_t)__shfl((int)h, 63, 64);
+    }
+    if (upto < 2) return;
+
+    // ---- RL (+ RS0), same chunk partition so every lane re-reads its own writes
+    carry = 0;
+    const uint32_t ctr2 = ((uint32_t)iter << 2) | 0u;
+    for (int x0 = ((W - 1) >> 6) << 6; x0 >= 0; x0 -= 64) {
+        const int x = x0 + lane;
+        const bool valid = x < W;
+        const int2 s = valid ? S[x] : make_int2(0, kInf);
+        const uint4 a = valid ? load_desc(DA, x) : make_uint4(0, 0, 0, 0);
+        const uint32_t f0 = (uint32_t)s.x;
+        const int32_t c0 = s.y;
+        const bool has_pred = valid && x + 1 < W;
+        uint32_t lp = f0, h = f0;
+        int32_t le = c0;
+        while (true) {
+            const uint32_t dn = (uint32_t)__shfl_down((int)h, 1, 64);
+            const uint32_t pred = lane == 63 ? carry : dn;
+            const bool need = has_pred && pred != lp;
+            if (!__any(need)) break;
+            if (need) {
+                lp = pred;
+                le = pred == f0 ? c0 : cost_at(DB, W, H, x, y, pred, a);
+            }
+            h = le < c0 ? lp : f0;
+        }
+        carry = (uint32_t)__shfl((int)h, 0, 64);
+        uint32_t bf = h;
+        int32_t bc = le < c0 ? le : c0;
+        if (upto >= 3 && valid) random_search<RC>(bf, bc, a, DB, W, H, x, y, (uint32_t)level, ctr2, sc);
+        if (valid) S[x] = make_int2((int)bf, bc);
+    }
+}
+
+// ------------------------------------------------------------ col phase --
+// TB sweep, random-search pass 1, BT sweep, random-search pass 2 of 64
+// columns per wave (lane = column, so every access is coalesced along the
+// row).  A lane holds R consecutive pixels of its column and solves the
+// sweep recursion on them by relaxation with the chunk boundary value
+// carried in (up to R independent gathers per round); the random search of
+// a pixel needs only that pixel's swept state and runs on the chunk right
+// after.  upto: 4 = TB, 5 = + RS1, 6 = + BT, 7 = + RS2.
+// grid (ceil(ceil(W / 64) / 4), 2 * pairs), 256 threads.
+template <int RC, int R>
+__global__ __launch_bounds__(256) void k_col_phase(const PairDev* __restrict__ pairs, int level, int iter,
+                                                   int upto, SearchConst sc)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, H = L.H;
+    const int lane = threadIdx.x & 63;
+    const int x = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + lane;
+    if (x - lane >= W) return;
+    const bool valid = x < W;
+    const uint8_t* __restrict__ DA = L.desc[dir];
+    const uint8_t* __restrict__ DB = L.desc[dir ^ 1];
+    int2* __restrict__ S = L.state[dir];
+
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && upto < 6) return;
+        const bool down = pass == 0;                 // TB, then BT
+        const bool do_rs = down ? upto >= 5 : upto >= 7;
+        const uint32_t ctr2 = ((uint32_t)iter << 2) | (down ? 1u : 2u);
+        uint32_t carry = 0;
+        const int nchunks = (H + R - 1) / R;
+        for (int ci = 0; ci < nchunks; ++ci) {
+            const int y0 = down ? ci * R : (nchunks - 1 - ci) * R;
+            uint32_t f0[R], lp[R], h[R];
+            int32_t c0[R], le[R];
+            uint4 a[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int y = y0 + k;
+                if (valid && y < H) {
+                    const int2 s = S[(size_t)y * W + x];
+                    f0[k] = (uint32_t)s.x;
+                    c0[k] = s.y;
+                    a[k] = load_desc(DA, (size_t)y * W + x);
+                } else {
+                    f0[k] = 0;
+                    c0[k] = kInf;
+                    a[k] = make_uint4(0, 0, 0, 0);
+                }
+                lp[k] = f0[k];
+                le[k] = c0[k];
+                h[k] = f0[k];
+            }
+            while (true) {
+                uint32_t pred[R];
+                bool need[R];
+                bool anyn = false;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int y = y0 + k;
+                    bool hp;
+                    if (down) {
+                        pred[k] = k == 0 ? carry : h[k - 1];
+                        hp = valid && y < H && y > 0;
+                    } else {
+                        pred[k] = k == R - 1 ? carry : h[k + 1];
+                        hp = valid && y + 1 < H;
+                    }
+                    need[k] = hp && pred[k] != lp[k];
+                    anyn |= need[k];
+                }
+                if (!__any(anyn)) break;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (need[k]) {
+                        lp[k] = pred[k];
+                        le[k] = pred[k] == f0[k] ? c0[k] : cost_at(DB, W, H, x, y0 + k, pred[k], a[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) h[k] = le[k] < c0[k] ? lp[k] : f0[k];
+            }
+            carry = down ? h[R - 1] : h[0];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int y = y0 + k;
+                if (!(valid && y < H)) continue;
+                uint32_t bf = h[k];
+                int32_t bc = le[k] < c0[k] ? le[k] : c0[k];
+                if (do_rs) random_search<RC>(bf, bc, a[k], DB, W, H, x, y, (uint32_t)level, ctr2, sc);
+                S[(size_t)y * W + x] = make_int2((int)bf, bc);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- consistency ----
+// Forward-backward check at level 0 (Sec. 3.1, threshold epsilon): p is kept
+// when its match and the match of q = p + F(p) are valid and
+// |F(p) + B(q)|^2 <= eps^2.  Writes the caller's flow / cost / mask.
+__global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[0];
+    const int W = L.W, H = L.H;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= W * H) return;
+    const int2 s = L.state[dir][i];
+    const uint32_t F = (uint32_t)s.x;
+    uint8_t m = 0;
+    if (s.y != kInf) {
+        const int x = i % W, y = i / W;
+        const int qx = x + flow_x(F), qy = y + flow_y(F);
+        const int2 t = L.state[dir ^ 1][(size_t)qy * W + qx];
+        if (t.y != kInf) {
+            const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
+            m = (ex * ex + ey * ey <= eps2) ? 1 : 0;
+        }
+    }
+    if (P.flow[dir]) reinterpret_cast<uint32_t*>(P.flow[dir])[i] = F;
+    if (P.cost[dir]) P.cost[dir][i] = s.y;
+    if (P.mask[dir]) P.mask[dir][i] = m;
+}
+
+// ------------------------------------------------------------- debug ----
+__global__ void k_copy_desc_signed(const uint8_t* __restrict__ src, int8_t* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = (int8_t)(src[i] ^ 0x80u);
+}
+
+__global__ void k_keys_to_index(const unsigned long long* __restrict__ keys, int32_t* __restrict__ dst, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)keys[i]);
+}
+
+// ------------------------------------------------------------ launchers --
+#define FF_GRID1(n) dim3((unsigned)(((n) + 255) / 256))
+
+void launch_gray(const PairDev* d, int npairs, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gray, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
+}
+void launch_down2(const PairDev* d, int npairs, int level, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_down2, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
+}
+void launch_desc(const PairDev* d, int npairs, int level, int maxW, int maxH, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_desc, dim3((maxW + kDescTX - 1) / kDescTX, (maxH + kDescTY - 1) / kDescTY, 2 * npairs),
+                       dim3(256), 0, st, d, level);
+}
+void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seed_records, dim3((maxN + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
+}
+void launch_seed_nn(const PairDev* d, int npairs, int level, int stride, int maxQ, int maxN, hipStream_t st)
+{
+    constexpr int MQ = 4;
+    const int qwaves = (maxQ + 16 * MQ - 1) / (16 * MQ);
+    const int ntiles = (maxN + 15) / 16;
+    int tps = 64;
+    int splits = (ntiles + tps - 1) / tps;
+    if (splits > 1024) {
+        splits = 1024;
+        tps = (ntiles + splits - 1) / splits;
+    }
+    if (tps > 2048) tps = 2048;
+    splits = (ntiles + tps - 1) / tps;
+    hipLaunchKernelGGL(k_seed_nn<MQ>, dim3((qwaves + 3) / 4, splits, 2 * npairs), dim3(256), 0, st, d, level,
+                       stride, tps);
+}
+void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stride, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
+}
+void launch_row_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
+                      int maxH, hipStream_t st)
+{
+    const dim3 grid((maxH + 3) / 4, 2 * npairs);
+    if (sc.radius == 16)
+        hipLaunchKernelGGL(k_row_phase<16>, grid, dim3(256), 0, st, d, level, iter, upto, sc);
+    else
+        hipLaunchKernelGGL(k_row_phase<0>, grid, dim3(256), 0, st, d, level, iter, upto, sc);
+}
+void launch_col_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
+                      int maxW, hipStream_t st)
+{
+    const int strips = (maxW + 63) / 64;
+    const dim3 grid((strips + 3) / 4, 2 * npairs);
+    if (sc.radius == 16)
+        hipLaunchKernelGGL((k_col_phase<16, 8>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+    else
+        hipLaunchKernelGGL((k_col_phase<0, 8>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+}
+void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fb, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, eps2);
+}
+void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_desc_signed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+}
+void launch_keys_to_index(const unsigned long long* keys, int32_t* dst, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_keys_to_index, dim3((n + 255) / 256), dim3(256), 0, st, keys, dst, n);
+}
+
+}  // namespace ff

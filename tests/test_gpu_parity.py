@@ -1,0 +1,280 @@
+"""GPU <-> oracle parity through the C ABI.  All outputs are integer, so the
+bar is bit-exactness: flows, costs and masks, and every intermediate the
+debug export exposes (luma, pyramid, descriptors, seed indices, search state
+after every step of every level and iteration).
+
+Each GPU step prints the case it runs (test, shape, parameters) first."""
+import numpy as np
+import pytest
+
+from paper_1805_03517_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU test run without a visible GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ffm():
+    from paper_1805_03517_amd import ff
+    return ff
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _prm(orc, levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED):
+    return orc.params(levels=levels, seed_stride=seed_stride, iters=iters, rs_radius=rs_radius,
+                      fb_eps=fb_eps, seed=seed)
+
+
+def _matcher(ffm, p):
+    return ffm.Matcher(levels=p.levels, seed_stride=p.seed_stride, iters=p.iters,
+                       rs_radius=p.rs_radius, fb_eps=p.fb_eps, seed=p.seed)
+
+
+def _compare_outputs(ref, got, tag):
+    for k in ("flow_f", "cost_f", "mask_f", "flow_b", "cost_b", "mask_b"):
+        g = got[k].cpu().numpy()
+        r = ref[k]
+        if not np.array_equal(g, r):
+            bad = np.argwhere(g != r)
+            raise AssertionError(f"{tag}: {k} differs at {len(bad)} places, first {bad[:3].tolist()}")
+
+
+def _run_pair(torch, ffm, orc, i1, i2, p, tag):
+    say(tag, "shape", i1.shape, "levels", p.levels, "stride", p.seed_stride, "R", p.rs_radius,
+        "eps", p.fb_eps, "entry ff_match_pair")
+    m = _matcher(ffm, p)
+    got = m.match(_dev(torch, i1), _dev(torch, i2))
+    torch.cuda.synchronize()
+    ref = orc.match(i1, i2, p)
+    _compare_outputs(ref, got, tag)
+    m.close()
+    return ref
+
+
+# ------------------------------------------------------ stage parity ----
+def test_stage_parity_config0(torch, ffm, orc):
+    i1, i2, _ = synth.config0()
+    p = _prm(orc, levels=3)
+    trace = {}
+
+    def tr(d, l, t, s, f, c):
+        trace[(d, l, t, s)] = (f, c)
+    orc.match(i1, i2, p, trace=tr)
+    m = _matcher(ffm, p)
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    grays = [orc.gray(i1), orc.gray(i2)]
+    pyrs = [orc.pyramid(g, 3) for g in grays]
+    for img in (0, 1):
+        say("stage gray image", img)
+        g = m.debug_stage(a, b, ffm.STAGE_GRAY, image=img).cpu().numpy()
+        assert np.array_equal(g, grays[img])
+        for l in range(3):
+            say("stage pyramid image", img, "level", l)
+            g = m.debug_stage(a, b, ffm.STAGE_PYRAMID, image=img, level=l).cpu().numpy()
+            assert np.array_equal(g, pyrs[img][l]), (img, l)
+            say("stage desc image", img, "level", l)
+            d = m.debug_stage(a, b, ffm.STAGE_DESC, image=img, level=l).cpu().numpy()
+            assert np.array_equal(d, orc.descriptors(pyrs[img][l])), (img, l)
+    D = [orc.descriptors(pyrs[i][2]) for i in (0, 1)]
+    for d in (0, 1):
+        say("stage seeds dir", d)
+        s = m.debug_stage(a, b, ffm.STAGE_SEEDS, dir=d).cpu().numpy()
+        assert np.array_equal(s, orc.seed_nn(D[d], D[1 - d], 3)), d
+    for d in (0, 1):
+        for l in (2, 1, 0):
+            steps = [(-1, 0)] + [(t, s) for t in range(2) for s in range(1, 8)]
+            for t, s in steps:
+                say("stage state dir", d, "level", l, "iter", t, "step", s)
+                st = m.debug_stage(a, b, ffm.STAGE_STATE, dir=d, level=l, iter=max(t, 0), step=s)
+                flow, cost = ffm.state_split(st)
+                rf, rc = trace[(d, l, t, s)]
+                if not (np.array_equal(flow, rf) and np.array_equal(cost, rc)):
+                    bad = np.argwhere((flow != rf).any(-1) | (cost != rc))
+                    raise AssertionError(f"state dir {d} level {l} iter {t} step {s}: "
+                                         f"{len(bad)} px differ, first {bad[:4].tolist()}")
+    m.close()
+
+
+# -------------------------------------------------- end-to-end parity ----
+def test_config0_end_to_end(torch, ffm, orc):
+    i1, i2, _ = synth.config0()
+    _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=3), "config0 128x96 gray")
+
+
+def test_config1_end_to_end(torch, ffm, orc):
+    i1, i2, _ = synth.config1()
+    ref = _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=4), "config1 1242x375 rgb")
+    assert ref["mask_f"].mean() > 0.3
+
+
+def test_config2_end_to_end(torch, ffm, orc):
+    i1, i2, _ = synth.config2()
+    _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=4), "config2 1024x436 rgb")
+
+
+EDGE_CASES = [
+    # (W, H, C, levels, stride, radius, eps, iters)
+    (64, 48, 1, 3, 3, 16, 1, 2),
+    (63, 47, 3, 3, 3, 16, 1, 2),       # odd sizes, ragged chunks
+    (65, 9, 1, 2, 3, 16, 1, 2),        # one pixel past a 64-wide chunk, few rows
+    (1, 1, 1, 1, 1, 16, 1, 2),         # single pixel
+    (5, 300, 1, 3, 2, 5, 0, 1),        # narrow and tall, runtime radius, eps 0
+    (300, 5, 3, 2, 1, 1, 3, 3),        # wide and flat, stride 1
+    (129, 130, 1, 1, 5, 0, 1, 2),      # one level, no random search
+    (200, 17, 1, 5, 3, 16, 2, 1),      # coarsest level 12x1
+    (8192, 8, 1, 4, 3, 16, 1, 1),      # maximum width
+    (6, 8192, 1, 2, 3, 3, 1, 1),       # maximum height, runtime radius
+    (97, 71, 3, 3, 4, 2, 1, 0),        # zero iterations: init only
+]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[f"{c[0]}x{c[1]}c{c[2]}L{c[3]}s{c[4]}R{c[5]}e{c[6]}T{c[7]}"
+                                                  for c in EDGE_CASES])
+def test_edge_shapes(torch, ffm, orc, case):
+    W, H, C, L, st, R, eps, T = case
+    rng = np.random.default_rng(W * 7919 + H)
+    d = (int(rng.integers(-6, 7)), int(rng.integers(-6, 7)))
+    if C == 1:
+        i1, i2, _ = synth.translated_pair(rng, W, H, d=d, rect=(min(16, W // 2), min(12, H // 2)), rect_d=(3, -2))
+    else:
+        chans = [synth.translated_pair(np.random.default_rng(k), W, H, d=d, rect=(0, 0)) for k in range(3)]
+        i1 = np.stack([c[0] for c in chans], -1)
+        i2 = np.stack([c[1] for c in chans], -1)
+    p = _prm(orc, levels=L, seed_stride=st, iters=T, rs_radius=R, fb_eps=eps)
+    _run_pair(torch, ffm, orc, i1, i2, p, f"edge {case}")
+
+
+def test_periodic_texture_seed_ties(torch, ffm, orc):
+    """A texture that repeats every 8 px makes many coarsest descriptors
+    identical: seed search ties must go to the lowest linear index."""
+    rng = np.random.default_rng(21)
+    tile = rng.integers(0, 256, size=(8, 8), dtype=np.uint8)
+    i1 = np.tile(tile, (12, 16))
+    i2 = np.roll(i1, (1, 2), axis=(0, 1)).copy()
+    p = _prm(orc, levels=2)
+    m = _matcher(ffm, p)
+    say("seed ties periodic 128x96")
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    g = [orc.pyramid(orc.gray(x), 2)[-1] for x in (i1, i2)]
+    D = [orc.descriptors(x) for x in g]
+    for d in (0, 1):
+        s = m.debug_stage(a, b, ffm.STAGE_SEEDS, dir=d).cpu().numpy()
+        assert np.array_equal(s, orc.seed_nn(D[d], D[1 - d], 3))
+    m.close()
+    _run_pair(torch, ffm, orc, i1, i2, p, "periodic texture")
+
+
+def test_identical_frames_zero_flow(torch, ffm, orc):
+    rng = np.random.default_rng(22)
+    img = synth._to_u8(synth.noise_texture(rng, 96, 160))
+    p = _prm(orc, levels=3)
+    say("identical frames 160x96")
+    m = _matcher(ffm, p)
+    o = m.match(_dev(torch, img), _dev(torch, img))
+    torch.cuda.synchronize()
+    assert int(o["flow_f"].abs().max()) == 0 and int(o["cost_f"].max()) == 0
+    assert int(o["mask_f"].min()) == 1
+    m.close()
+
+
+# ------------------------------------------------- batch and determinism ----
+def test_batch_equals_single_pairs(torch, ffm, orc):
+    rng = np.random.default_rng(23)
+    pairs = []
+    for k in range(7):
+        W, H = int(rng.integers(40, 260)), int(rng.integers(40, 200))
+        d = (int(rng.integers(-20, 21)), int(rng.integers(-20, 21)))
+        i1, i2, _ = synth.translated_pair(np.random.default_rng(k), W, H, d=d)
+        pairs.append((i1, i2))
+    p = _prm(orc, levels=3)
+    m = _matcher(ffm, p)
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b in pairs]
+    say("batch of 7 uneven gray pairs, entry ff_match_batch")
+    outs = m.match_batch(dev)
+    torch.cuda.synchronize()
+    for k, ((a, b), o) in enumerate(zip(pairs, outs)):
+        say("batch member", k, a.shape)
+        ref = orc.match(a, b, p)
+        _compare_outputs(ref, o, f"batch member {k}")
+    # the same batch again, in a different order, reuses the workspace
+    say("batch reordered")
+    outs2 = m.match_batch(dev[::-1])
+    torch.cuda.synchronize()
+    for o1, o2 in zip(outs, outs2[::-1]):
+        for key in o1:
+            assert torch.equal(o1[key], o2[key])
+    m.close()
+
+
+def test_batch_of_config1_pairs_full_size(torch, ffm, orc):
+    """The launch configuration the benchmark times: a batch of 1242x375 RGB
+    pairs through ff_match_batch; two members are checked in full."""
+    pairs = [synth.config1(seed=100 + k)[:2] for k in range(8)]
+    p = _prm(orc, levels=4)
+    m = _matcher(ffm, p)
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b in pairs]
+    say("batch of 8 config1 pairs, entry ff_match_batch")
+    outs = m.match_batch(dev)
+    torch.cuda.synchronize()
+    for k in (0, 5):
+        say("check member", k)
+        _compare_outputs(orc.match(pairs[k][0], pairs[k][1], p), outs[k], f"config1 batch member {k}")
+    m.close()
+
+
+def test_repeat_runs_are_bitwise_identical(torch, ffm, orc):
+    i1, i2, _ = synth.config1(seed=7)
+    p = _prm(orc, levels=4)
+    m = _matcher(ffm, p)
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    say("determinism config1 x5")
+    first = m.match(a, b)
+    for _ in range(4):
+        o = m.match(a, b)
+        for key in first:
+            assert torch.equal(first[key], o[key]), key
+    torch.cuda.synchronize()
+    m.close()
+
+
+def test_swap_invariant_on_gpu(torch, ffm, orc):
+    i1, i2, _ = synth.config0()
+    p = _prm(orc, levels=3)
+    m = _matcher(ffm, p)
+    say("swap invariant config0")
+    a = m.match(_dev(torch, i1), _dev(torch, i2))
+    b = m.match(_dev(torch, i2), _dev(torch, i1))
+    torch.cuda.synchronize()
+    assert torch.equal(a["flow_b"], b["flow_f"]) and torch.equal(a["cost_b"], b["cost_f"])
+    assert torch.equal(a["mask_b"], b["mask_f"])
+    m.close()
+
+
+def test_invalid_arguments_are_rejected(torch, ffm):
+    m = ffm.Matcher(levels=4)
+    small = torch.zeros((4, 4), dtype=torch.uint8, device="cuda")
+    say("invalid: too small for levels")
+    with pytest.raises(ffm.FFError) as e:
+        m.match(small, small)
+    assert e.value.status == ffm.FF_ERR_INVALID
+    say("invalid: budget")
+    tight = ffm.Matcher(levels=2, hbm_budget=1024)
+    img = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ffm.FFError) as e:
+        tight.match(img, img)
+    assert e.value.status == ffm.FF_ERR_BUDGET
+    m.close()
+    tight.close()
