@@ -110,7 +110,7 @@ uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
  * events, writes one entry per kernel (launch count and summed device time
  * between its events) into out[0..max), returns the number of entries, and
  * clears the record.  Names: gray, down2, desc, seed_records, seed_nn, init,
- * row_phase, col_phase, fb.  Returns -1 on error.                           */
+ * row_phase, col_phase, transpose, fb.  Returns -1 on error.                */
 typedef struct {
     char    name[32];
     int32_t launches;

@@ -5,12 +5,16 @@
 //   gray[l][i]   uint8  [H_l][W_l]        pyramid level l of image i
 //   desc[l][i]   uint8  [H_l][W_l][16]    descriptors, stored biased (d + 128)
 //                                         so the SAD unit works on unsigned bytes
+//   descT[l][i]  uint8  [W_l][H_l][16]    the same descriptors column-major
 //   state[l][d]  int2   [H_l][W_l]        search state of direction d:
 //                                         .x = flow (int16 dx | int16 dy << 16),
 //                                         .y = cost (INT32_MAX = invalid)
+//   stateT[l][d] int2   [W_l][H_l]        column-major copy used by the column phase
 //   dbrec[i]     int8   [N][64]           seed-search database records of image i
 //                                         at the coarsest level (see k_seed_records)
 //   keys[d]      uint64 [nsy][nsx]        packed (score, ~index) of the best seed match
+// The column phase runs the same line kernel as the row phase on the
+// column-major copies, so its lanes walk consecutive y with coalesced loads.
 #pragma once
 #include <stdint.h>
 
@@ -24,7 +28,9 @@ struct LevelDev {
     int W, H;
     uint8_t* gray[2];
     uint8_t* desc[2];
+    uint8_t* descT[2];
     int2* state[2];
+    int2* stateT[2];
 };
 
 struct PairDev {

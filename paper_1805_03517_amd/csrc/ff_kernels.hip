@@ -34,15 +34,23 @@ __device__ __forceinline__ int32_t sad16(uint4 a, uint4 b)
     return (int32_t)s;
 }
 
+// Index of pixel (x, y) in a row-major ([H][W]) or column-major ([W][H]) plane.
+template <bool COL>
+__device__ __forceinline__ size_t pix(int x, int y, int W, int H)
+{
+    return COL ? (size_t)x * H + y : (size_t)y * W + x;
+}
+
 // Matching cost of pixel (x, y) of A under flow f against descriptor plane
 // DB (Sec. 3.1: a distance of feature descriptors).  INF when the target
-// leaves the image; no load is issued then.
+// leaves the image; no load is issued then.  COL selects DB's layout.
+template <bool COL = false>
 __device__ __forceinline__ int32_t cost_at(const uint8_t* __restrict__ DB, int W, int H, int x, int y,
                                            uint32_t f, uint4 a)
 {
     int qx = x + flow_x(f), qy = y + flow_y(f);
     if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-    uint4 b = *reinterpret_cast<const uint4*>(DB + ((size_t)qy * W + qx) * 16);
+    uint4 b = *reinterpret_cast<const uint4*>(DB + pix<COL>(qx, qy, W, H) * 16);
     return sad16(a, b);
 }
 
@@ -73,7 +81,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // (2,3) for odd j.  All trial costs are gathered first (independent loads),
 // then selected in trial order with a strict '<', which equals the
 // sequential rule because a trial equal to the running best costs the same.
-template <int RC>
+template <int RC, bool COL = false>
 __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a,
                                               const uint8_t* __restrict__ DB, int W, int H, int x,
                                               int y, uint32_t level, uint32_t ctr2,
@@ -96,7 +104,7 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a
             const int r = RC >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
             cand[j] = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            e[j] = cost_at(DB, W, H, x, y, cand[j], a);
+            e[j] = cost_at<COL>(DB, W, H, x, y, cand[j], a);
         }
 #pragma unroll
         for (int j = 0; j < JC; ++j)
@@ -111,7 +119,7 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a
             const int r = R >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
             const uint32_t c = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            const int32_t ej = cost_at(DB, W, H, x, y, c, a);
+            const int32_t ej = cost_at<COL>(DB, W, H, x, y, c, a);
             if (ej < bc) { bc = ej; bf = c; }
         }
     }
@@ -158,7 +166,9 @@ __global__ __launch_bounds__(256) void k_down2(const PairDev* __restrict__ pairs
 // separable: the four lowest-sequency Walsh functions on 8 samples are
 // constant on sample pairs, so a 1-D transform is 4 pair sums and one
 // 4-point butterfly.  A block covers 64 x 16 outputs; its 71 x 23 input
-// window (replicated border) and the 23 x 64 row transforms live in LDS.
+// window (replicated border), the 23 x 64 row transforms and the finished
+// descriptors live in LDS.  Written twice: row-major (lanes along x) and
+// column-major (lanes along y), both coalesced.
 constexpr int kDescTX = 64, kDescTY = 16;
 
 __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs, int level)
@@ -189,11 +199,9 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
         rowt[r][c][3] = (int16_t)(q0 - q1 + q2 - q3);
     }
     __syncthreads();
-    uint8_t* dst = L.desc[img];
+    __shared__ uint4 res[kDescTY][kDescTX];
     for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {
         const int c = i % kDescTX, r = i / kDescTX;
-        const int x = x0 + c, y = y0 + r;
-        if (x >= W || y >= H) continue;
         uint32_t words[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -208,7 +216,20 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
                 words[k >> 2] |= (uint32_t)(d & 0xFF) << (8 * (k & 3));
             }
         }
-        *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = make_uint4(words[0], words[1], words[2], words[3]);
+        res[r][c] = make_uint4(words[0], words[1], words[2], words[3]);
+    }
+    __syncthreads();
+    uint8_t* dst = L.desc[img];
+    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {         // row-major: lanes along x
+        const int c = i % kDescTX, r = i / kDescTX;
+        const int x = x0 + c, y = y0 + r;
+        if (x < W && y < H) *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = res[r][c];
+    }
+    uint8_t* dstT = L.descT[img];
+    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {         // column-major: lanes along y
+        const int r = i % kDescTY, c = i / kDescTY;
+        const int x = x0 + c, y = y0 + r;
+        if (x < W && y < H) *reinterpret_cast<uint4*>(dstT + ((size_t)x * H + y) * 16) = res[r][c];
     }
 }
 
@@ -372,187 +393,165 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
     L.state[dir][i] = make_int2((int)f, c);
 }
 
-// ------------------------------------------------------------ row phase --
-// LR sweep, RL sweep and random-search pass 0 of one line per wave.
-// Sweep semantics (propagation, Sec. 3.1): scanning the line, a pixel takes
-// its predecessor's post-update flow iff that flow's cost is strictly lower
-// than the pixel's own pre-sweep cost.  The result is the unique solution h
-// of h_x = rule(pre_x, h_{x-1}); a 64-pixel chunk solves it by relaxation
-// (every lane re-applies the rule to its own pre-sweep value and its
-// neighbour's current value, DPP shift between lanes) until no lane's
-// neighbour value changes, with the chunk boundary value carried in.  The
-// count of rounds is one plus the longest propagation run in the chunk.
-// upto: 1 = LR only, 2 = LR + RL, 3 = LR + RL + RS0.
-// grid (ceil(H / 4), 2 * pairs), 256 threads (4 lines).
-template <int RC>
-__global__ __launch_bounds__(256) void k_row_phase(const PairDev* __restrict__ pairs, int level, int iter,
-                                                   int upto, SearchConst sc)
+// ------------------------------------------------------- line phases ----
+// Blocks are dispatched to the 8 XCDs round-robin by linear block id; the
+// remap gives each XCD a contiguous range of logical blocks, so the lines of
+// one pair and direction (which gather from the same descriptor plane) run
+// on one XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
 {
-    const PairDev& P = pairs[blockIdx.y >> 1];
-    const int dir = blockIdx.y & 1;
-    const LevelDev& L = P.lv[level];
-    const int W = L.W, H = L.H;
-    const int lane = threadIdx.x & 63;
-    const int y = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (y >= H) return;
-    const uint8_t* __restrict__ DA = L.desc[dir] + (size_t)y * W * 16;
-    const uint8_t* __restrict__ DB = L.desc[dir ^ 1];
-    int2* __restrict__ S = L.state[dir] + (size_t)y * W;
-
-    // ---- LR
-    uint32_t carry = 0;
-    for (int x0 = 0; x0 < W; x0 += 64) {
-        const int x = x0 + lane;
-        const bool valid = x < W;
-        const int2 s = valid ? S[x] : make_int2(0, kInf);
-        const uint4 a = valid ? load_desc(DA, x) : make_uint4(0, 0, 0, 0);
-        const uint32_t f0 = (uint32_t)s.x;
-        const int32_t c0 = s.y;
-        const bool has_pred = valid && x > 0;
-        uint32_t lp = f0, h = f0;
-        int32_t le = c0;
-        while (true) {
-            const uint32_t up = (uint32_t)__shfl_up((int)h, 1, 64);
-            const uint32_t pred = lane == 0 ? carry : up;
-            const bool need = has_pred && pred != lp;
-            if (!__any(need)) break;
-            if (need) {
-                lp = pred;
-                le = pred == f0 ? c0 : cost_at(DB, W, H, x, y, pred, a);
-            }
-            h = le < c0 ? lp : f0;
-        }
-        if (valid) S[x] = make_int2((int)h, le < c0 ? le : c0);
-        carry = (uint32_t)__shfl((int)h, 63, 64);
-    }
-    if (upto < 2) return;
-
-    // ---- RL (+ RS0), same chunk partition so every lane re-reads its own writes
-    carry = 0;
-    const uint32_t ctr2 = ((uint32_t)iter << 2) | 0u;
-    for (int x0 = ((W - 1) >> 6) << 6; x0 >= 0; x0 -= 64) {
-        const int x = x0 + lane;
-        const bool valid = x < W;
-        const int2 s = valid ? S[x] : make_int2(0, kInf);
-        const uint4 a = valid ? load_desc(DA, x) : make_uint4(0, 0, 0, 0);
-        const uint32_t f0 = (uint32_t)s.x;
-        const int32_t c0 = s.y;
-        const bool has_pred = valid && x + 1 < W;
-        uint32_t lp = f0, h = f0;
-        int32_t le = c0;
-        while (true) {
-            const uint32_t dn = (uint32_t)__shfl_down((int)h, 1, 64);
-            const uint32_t pred = lane == 63 ? carry : dn;
-            const bool need = has_pred && pred != lp;
-            if (!__any(need)) break;
-            if (need) {
-                lp = pred;
-                le = pred == f0 ? c0 : cost_at(DB, W, H, x, y, pred, a);
-            }
-            h = le < c0 ? lp : f0;
-        }
-        carry = (uint32_t)__shfl((int)h, 0, 64);
-        uint32_t bf = h;
-        int32_t bc = le < c0 ? le : c0;
-        if (upto >= 3 && valid) random_search<RC>(bf, bc, a, DB, W, H, x, y, (uint32_t)level, ctr2, sc);
-        if (valid) S[x] = make_int2((int)bf, bc);
-    }
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
-// ------------------------------------------------------------ col phase --
-// TB sweep, random-search pass 1, BT sweep, random-search pass 2 of 64
-// columns per wave (lane = column, so every access is coalesced along the
-// row).  A lane holds R consecutive pixels of its column and solves the
-// sweep recursion on them by relaxation with the chunk boundary value
-// carried in (up to R independent gathers per round); the random search of
-// a pixel needs only that pixel's swept state and runs on the chunk right
-// after.  upto: 4 = TB, 5 = + RS1, 6 = + BT, 7 = + RS2.
-// grid (ceil(ceil(W / 64) / 4), 2 * pairs), 256 threads.
-template <int RC, int R>
-__global__ __launch_bounds__(256) void k_col_phase(const PairDev* __restrict__ pairs, int level, int iter,
-                                                   int upto, SearchConst sc)
+// One phase of one iteration, one wave per line.
+//   row phase (COL = false, lines = rows, row-major buffers):
+//       LR sweep; RL sweep followed by random-search pass 0
+//   col phase (COL = true, lines = columns, column-major buffers):
+//       TB sweep followed by pass 1; BT sweep followed by pass 2
+// Sweep semantics (propagation, Sec. 3.1): scanning the line, a pixel takes
+// its predecessor's post-update flow iff that flow's cost is strictly lower
+// than the pixel's own pre-sweep cost.  The result is the unique h with
+// h_p = rule(pre_p, h_{p-1}); a window of CH x 64 pixels (lane l holds
+// positions w0 + 64c + l) solves it by relaxation -- every pixel re-applies
+// the rule to its own pre-sweep value and its predecessor's current value
+// until no predecessor value changes -- with the boundary value carried in
+// from the previous window.  Rounds = 1 + longest propagation run in the
+// window; only pixels whose predecessor changed gather again.  A pixel's
+// random search needs only its own swept state, so it runs on the window
+// right after convergence, before the write.  Both passes use the same
+// window partition, so every lane re-reads exactly what it wrote.
+// upto (for intermediate captures): row 1 = LR, 2 = +RL, 3 = +RS0;
+// col 4 = TB, 5 = +RS1, 6 = +BT, 7 = +RS2.
+// grid (ceil(lines / 4), 2 * pairs), 256 threads.
+template <int RC, bool COL, int CH>
+__global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ pairs, int level, int iter,
+                                                    int upto, SearchConst sc)
 {
-    const PairDev& P = pairs[blockIdx.y >> 1];
-    const int dir = blockIdx.y & 1;
+    const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int pd = lb / gridDim.x, bx = lb % gridDim.x;
+    const PairDev& P = pairs[pd >> 1];
+    const int dir = pd & 1;
     const LevelDev& L = P.lv[level];
     const int W = L.W, H = L.H;
+    const int len = COL ? H : W, nlines = COL ? W : H;
     const int lane = threadIdx.x & 63;
-    const int x = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + lane;
-    if (x - lane >= W) return;
-    const bool valid = x < W;
-    const uint8_t* __restrict__ DA = L.desc[dir];
-    const uint8_t* __restrict__ DB = L.desc[dir ^ 1];
-    int2* __restrict__ S = L.state[dir];
+    const int line = bx * 4 + (threadIdx.x >> 6);
+    if (line >= nlines) return;
+    const uint8_t* __restrict__ DA = (COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
+    const uint8_t* __restrict__ DB = COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1];
+    int2* __restrict__ S = (COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
+    constexpr int WIN = 64 * CH;
+    const int nwin = (len + WIN - 1) / WIN;
 
     for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 && upto < 6) return;
-        const bool down = pass == 0;                 // TB, then BT
-        const bool do_rs = down ? upto >= 5 : upto >= 7;
-        const uint32_t ctr2 = ((uint32_t)iter << 2) | (down ? 1u : 2u);
+        const bool fwd = pass == 0;
+        bool rs;
+        uint32_t rs_pass;
+        if (!COL) {
+            if (!fwd && upto < 2) break;
+            rs = !fwd && upto >= 3;
+            rs_pass = 0;
+        } else {
+            if (!fwd && upto < 6) break;
+            rs = fwd ? upto >= 5 : upto >= 7;
+            rs_pass = fwd ? 1 : 2;
+        }
+        const uint32_t ctr2 = ((uint32_t)iter << 2) | rs_pass;
         uint32_t carry = 0;
-        const int nchunks = (H + R - 1) / R;
-        for (int ci = 0; ci < nchunks; ++ci) {
-            const int y0 = down ? ci * R : (nchunks - 1 - ci) * R;
-            uint32_t f0[R], lp[R], h[R];
-            int32_t c0[R], le[R];
-            uint4 a[R];
+        for (int wi = 0; wi < nwin; ++wi) {
+            const int w0 = (fwd ? wi : nwin - 1 - wi) * WIN;
+            uint32_t f0[CH], lp[CH], h[CH];
+            int32_t c0[CH], le[CH];
+            uint4 a[CH];
+            bool hp[CH];
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int y = y0 + k;
-                if (valid && y < H) {
-                    const int2 s = S[(size_t)y * W + x];
-                    f0[k] = (uint32_t)s.x;
-                    c0[k] = s.y;
-                    a[k] = load_desc(DA, (size_t)y * W + x);
-                } else {
-                    f0[k] = 0;
-                    c0[k] = kInf;
-                    a[k] = make_uint4(0, 0, 0, 0);
-                }
-                lp[k] = f0[k];
-                le[k] = c0[k];
-                h[k] = f0[k];
+            for (int c = 0; c < CH; ++c) {
+                const int p = w0 + 64 * c + lane;
+                const bool valid = p < len;
+                const int2 st = valid ? S[p] : make_int2(0, kInf);
+                a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
+                f0[c] = (uint32_t)st.x;
+                c0[c] = st.y;
+                hp[c] = valid && (fwd ? p > 0 : p + 1 < len);
+                lp[c] = f0[c];
+                le[c] = c0[c];
+                h[c] = f0[c];
             }
             while (true) {
-                uint32_t pred[R];
-                bool need[R];
+                uint32_t pred[CH];
+                bool need[CH];
                 bool anyn = false;
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int y = y0 + k;
-                    bool hp;
-                    if (down) {
-                        pred[k] = k == 0 ? carry : h[k - 1];
-                        hp = valid && y < H && y > 0;
+                for (int c = 0; c < CH; ++c) {
+                    if (fwd) {
+                        const uint32_t up = (uint32_t)__shfl_up((int)h[c], 1, 64);
+                        const uint32_t edge = c == 0 ? carry : (uint32_t)__builtin_amdgcn_readlane((int)h[c > 0 ? c - 1 : 0], 63);
+                        pred[c] = lane == 0 ? edge : up;
                     } else {
-                        pred[k] = k == R - 1 ? carry : h[k + 1];
-                        hp = valid && y + 1 < H;
+                        const uint32_t dn = (uint32_t)__shfl_down((int)h[c], 1, 64);
+                        const uint32_t edge = c == CH - 1 ? carry
+                                                          : (uint32_t)__builtin_amdgcn_readlane((int)h[c < CH - 1 ? c + 1 : c], 0);
+                        pred[c] = lane == 63 ? edge : dn;
                     }
-                    need[k] = hp && pred[k] != lp[k];
-                    anyn |= need[k];
+                    need[c] = hp[c] && pred[c] != lp[c];
+                    anyn |= need[c];
                 }
                 if (!__any(anyn)) break;
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    if (need[k]) {
-                        lp[k] = pred[k];
-                        le[k] = pred[k] == f0[k] ? c0[k] : cost_at(DB, W, H, x, y0 + k, pred[k], a[k]);
+                for (int c = 0; c < CH; ++c) {
+                    if (need[c]) {
+                        const int p = w0 + 64 * c + lane;
+                        lp[c] = pred[c];
+                        le[c] = pred[c] == f0[c] ? c0[c]
+                                                 : cost_at<COL>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < R; ++k) h[k] = le[k] < c0[k] ? lp[k] : f0[k];
+                for (int c = 0; c < CH; ++c) h[c] = le[c] < c0[c] ? lp[c] : f0[c];
             }
-            carry = down ? h[R - 1] : h[0];
+            carry = fwd ? (uint32_t)__builtin_amdgcn_readlane((int)h[CH - 1], 63)
+                        : (uint32_t)__builtin_amdgcn_readlane((int)h[0], 0);
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int y = y0 + k;
-                if (!(valid && y < H)) continue;
-                uint32_t bf = h[k];
-                int32_t bc = le[k] < c0[k] ? le[k] : c0[k];
-                if (do_rs) random_search<RC>(bf, bc, a[k], DB, W, H, x, y, (uint32_t)level, ctr2, sc);
-                S[(size_t)y * W + x] = make_int2((int)bf, bc);
+            for (int c = 0; c < CH; ++c) {
+                const int p = w0 + 64 * c + lane;
+                if (p >= len) continue;
+                uint32_t bf = h[c];
+                int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
+                if (rs)
+                    random_search<RC, COL>(bf, bc, a[c], DB, W, H, COL ? line : p, COL ? p : line, (uint32_t)level,
+                                           ctr2, sc);
+                S[p] = make_int2((int)bf, bc);
             }
         }
+    }
+}
+
+// State transpose between the row-major and column-major copies of every
+// pair and direction at one level (32 x 32 tiles through LDS).
+// to_t = 1: state -> stateT, grid (ceil(W/32), ceil(H/32), 2 * pairs);
+// to_t = 0: stateT -> state, grid (ceil(H/32), ceil(W/32), 2 * pairs).
+__global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restrict__ pairs, int level, int to_t)
+{
+    const PairDev& P = pairs[blockIdx.z >> 1];
+    const int dir = blockIdx.z & 1;
+    const LevelDev& L = P.lv[level];
+    const int SW = to_t ? L.W : L.H, SH = to_t ? L.H : L.W;     // source is [SH][SW]
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    if (x0 >= SW || y0 >= SH) return;
+    const int2* __restrict__ src = to_t ? L.state[dir] : L.stateT[dir];
+    int2* __restrict__ dst = to_t ? L.stateT[dir] : L.state[dir];
+    __shared__ int2 t[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int y = y0 + r, x = x0 + tx;
+        if (y < SH && x < SW) t[r][tx] = src[(size_t)y * SW + x];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int xx = x0 + r, yy = y0 + tx;                     // destination is [SW][SH]
+        if (xx < SW && yy < SH) dst[(size_t)xx * SH + yy] = t[tx][r];
     }
 }
 
@@ -641,21 +640,28 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
 void launch_row_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
                       int maxH, hipStream_t st)
 {
+    constexpr int CH = 4;
     const dim3 grid((maxH + 3) / 4, 2 * npairs);
     if (sc.radius == 16)
-        hipLaunchKernelGGL(k_row_phase<16>, grid, dim3(256), 0, st, d, level, iter, upto, sc);
+        hipLaunchKernelGGL((k_line_phase<16, false, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
     else
-        hipLaunchKernelGGL(k_row_phase<0>, grid, dim3(256), 0, st, d, level, iter, upto, sc);
+        hipLaunchKernelGGL((k_line_phase<0, false, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
 }
 void launch_col_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
                       int maxW, hipStream_t st)
 {
-    const int strips = (maxW + 63) / 64;
-    const dim3 grid((strips + 3) / 4, 2 * npairs);
+    constexpr int CH = 4;
+    const dim3 grid((maxW + 3) / 4, 2 * npairs);
     if (sc.radius == 16)
-        hipLaunchKernelGGL((k_col_phase<16, 8>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+        hipLaunchKernelGGL((k_line_phase<16, true, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
     else
-        hipLaunchKernelGGL((k_col_phase<0, 8>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+        hipLaunchKernelGGL((k_line_phase<0, true, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+}
+void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
+{
+    const int sw = to_t ? maxW : maxH, sh = to_t ? maxH : maxW;
+    hipLaunchKernelGGL(k_transpose_state, dim3((sw + 31) / 32, (sh + 31) / 32, 2 * npairs), dim3(256), 0, st, d,
+                       level, to_t);
 }
 void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
 {

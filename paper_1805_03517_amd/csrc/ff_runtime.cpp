@@ -5,7 +5,8 @@
 // grown on demand and kept), writes the per-pair device table, and enqueues
 // the fixed launch sequence on the caller's stream:
 //   gray -> pyramid (L-1) -> descriptors (L) -> seed records -> seed NN
-//   -> for each level, coarsest first: init, then iters x (row phase, col phase)
+//   -> for each level, coarsest first: init, then iters x (row phase,
+//      state -> column-major, col phase, state -> row-major)
 //   -> forward-backward check.
 // Every launch covers all pairs of the batch, so a batch costs the same
 // number of launches as one pair.
@@ -29,6 +30,7 @@ void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_row_phase(const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
 void launch_col_phase(const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
+void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
@@ -96,8 +98,8 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
         pl.H[l] = l == 0 ? H : pl.H[l - 1] >> 1;
         const size_t n = (size_t)pl.W[l] * pl.H[l];
         b += 2 * align_up(n);            // gray planes
-        b += 2 * align_up(n * 16);       // descriptors
-        b += 2 * align_up(n * 8);        // state
+        b += 4 * align_up(n * 16);       // descriptors, row- and column-major
+        b += 4 * align_up(n * 8);        // state, row- and column-major
     }
     const int c = p.levels - 1;
     pl.nsx = (pl.W[c] + p.seed_stride - 1) / p.seed_stride;
@@ -196,7 +198,9 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
             L.H = pl.H[l];
             for (int k = 0; k < 2; ++k) L.gray[k] = (uint8_t*)take(np);
             for (int k = 0; k < 2; ++k) L.desc[k] = (uint8_t*)take(np * 16);
+            for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(np * 16);
             for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take(np * 8);
+            for (int k = 0; k < 2; ++k) L.stateT[k] = (int2*)take(np * 8);
         }
         const int c = p.levels - 1;
         for (int k = 0; k < 2; ++k) d.dbrec[k] = (int8_t*)take((size_t)pl.W[c] * pl.H[c] * 64);
@@ -266,8 +270,8 @@ SearchConst search_const(const ff_params& p)
 }
 
 const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn",
-                                    "init", "row_phase", "col_phase", "fb"};
-enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_FB, KN_COUNT };
+                                    "init", "row_phase", "col_phase", "transpose", "fb"};
+enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, hipStream_t st)
@@ -370,7 +374,11 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
             const bool last = stop_here && stop.st.iter == t;
             const int upto = last ? stop.st.step : 7;
             FF_TRACED(KN_ROW, launch_row_phase(d, n, l, t, std::min(upto, 3), sc, maxH[l], st));
-            if (upto >= 4) FF_TRACED(KN_COL, launch_col_phase(d, n, l, t, upto, sc, maxW[l], st));
+            if (upto >= 4) {
+                FF_TRACED(KN_TRANS, launch_transpose_state(d, n, l, 1, maxW[l], maxH[l], st));
+                FF_TRACED(KN_COL, launch_col_phase(d, n, l, t, upto, sc, maxW[l], st));
+                FF_TRACED(KN_TRANS, launch_transpose_state(d, n, l, 0, maxW[l], maxH[l], st));
+            }
             if (last) {
                 FF_HIP(h, hipMemcpyAsync(stop.dst, tab[0].lv[l].state[stop.st.dir],
                                          (size_t)plans[0].W[l] * plans[0].H[l] * 8, hipMemcpyDeviceToDevice, st));
