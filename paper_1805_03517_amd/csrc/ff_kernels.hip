@@ -24,6 +24,22 @@ __device__ __forceinline__ uint32_t pack_flow(int fx, int fy)
 __device__ __forceinline__ int flow_x(uint32_t f) { return (int)(int16_t)(f & 0xFFFFu); }
 __device__ __forceinline__ int flow_y(uint32_t f) { return (int)(int16_t)(f >> 16); }
 
+// Global-address-space pointers.  Buffer pointers arrive through the
+// per-pair table as generic pointers; converting the base pointer once makes
+// every access below a global_load / global_store instead of a flat one.
+#define FF_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef FF_GLOBAL const uint8_t gcu8;
+typedef FF_GLOBAL const u32x4 gcu4;
+typedef FF_GLOBAL i32x2 gi2;
+
+__device__ __forceinline__ uint4 ld16(gcu8* p)
+{
+    const u32x4 v = *(gcu4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // SAD of two 16-byte descriptors held biased (unsigned) -- four v_sad_u8.
 __device__ __forceinline__ int32_t sad16(uint4 a, uint4 b)
 {
@@ -45,18 +61,17 @@ __device__ __forceinline__ size_t pix(int x, int y, int W, int H)
 // DB (Sec. 3.1: a distance of feature descriptors).  INF when the target
 // leaves the image; no load is issued then.  COL selects DB's layout.
 template <bool COL = false>
-__device__ __forceinline__ int32_t cost_at(const uint8_t* __restrict__ DB, int W, int H, int x, int y,
-                                           uint32_t f, uint4 a)
+__device__ __forceinline__ int32_t cost_at(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f, uint4 a)
 {
     int qx = x + flow_x(f), qy = y + flow_y(f);
     if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-    uint4 b = *reinterpret_cast<const uint4*>(DB + pix<COL>(qx, qy, W, H) * 16);
+    const uint4 b = ld16(DB + pix<COL>(qx, qy, W, H) * 16);
     return sad16(a, b);
 }
 
-__device__ __forceinline__ uint4 load_desc(const uint8_t* __restrict__ D, size_t idx)
+__device__ __forceinline__ uint4 load_desc(gcu8* __restrict__ D, size_t idx)
 {
-    return *reinterpret_cast<const uint4*>(D + idx * 16);
+    return ld16(D + idx * 16);
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4-word S-P network,
@@ -65,9 +80,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -83,7 +99,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // sequential rule because a trial equal to the running best costs the same.
 template <int RC, bool COL = false>
 __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a,
-                                              const uint8_t* __restrict__ DB, int W, int H, int x,
+                                              gcu8* __restrict__ DB, int W, int H, int x,
                                               int y, uint32_t level, uint32_t ctr2,
                                               const SearchConst& sc)
 {
@@ -249,7 +265,7 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n < P.nsx * P.nsy) P.keys[img][n] = 0ull;
     if (n >= N) return;
-    const uint4 db = load_desc(L.desc[img], n);
+    const uint4 db = load_desc((gcu8*)L.desc[img], n);
     const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
     const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
     int nb = 0;
@@ -310,7 +326,7 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
             A[mq] = v4i{0x7F7F7F7F, 0x7F7F7F7F, 0x7F7F7F7F, g == 2 ? 0x7F7F7F7F : 0x017F7F7F};
         } else if (q < Q) {
             const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
-            const uint4 d = load_desc(L.desc[dir], (size_t)sy * W + sx);
+            const uint4 d = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
             A[mq] = v4i{(int)(d.x ^ 0x80808080u), (int)(d.y ^ 0x80808080u), (int)(d.z ^ 0x80808080u),
                         (int)(d.w ^ 0x80808080u)};
         } else {
@@ -389,7 +405,7 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
         const uint32_t cf = (uint32_t)C.state[dir][(size_t)cy * C.W + cx].x;
         f = pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
     }
-    const int32_t c = cost_at(L.desc[dir ^ 1], W, H, x, y, f, load_desc(L.desc[dir], i));
+    const int32_t c = cost_at((gcu8*)L.desc[dir ^ 1], W, H, x, y, f, load_desc((gcu8*)L.desc[dir], i));
     L.state[dir][i] = make_int2((int)f, c);
 }
 
@@ -439,9 +455,9 @@ __global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ 
     const int lane = threadIdx.x & 63;
     const int line = bx * 4 + (threadIdx.x >> 6);
     if (line >= nlines) return;
-    const uint8_t* __restrict__ DA = (COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
-    const uint8_t* __restrict__ DB = COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1];
-    int2* __restrict__ S = (COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
+    gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
+    gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
+    gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
     constexpr int WIN = 64 * CH;
     const int nwin = (len + WIN - 1) / WIN;
 
@@ -470,7 +486,7 @@ __global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ 
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = p < len;
-                const int2 st = valid ? S[p] : make_int2(0, kInf);
+                const i32x2 st = valid ? S[p] : i32x2{0, kInf};
                 a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
                 f0[c] = (uint32_t)st.x;
                 c0[c] = st.y;
@@ -522,7 +538,7 @@ __global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ 
                 if (rs)
                     random_search<RC, COL>(bf, bc, a[c], DB, W, H, COL ? line : p, COL ? p : line, (uint32_t)level,
                                            ctr2, sc);
-                S[p] = make_int2((int)bf, bc);
+                S[p] = i32x2{(int)bf, bc};
             }
         }
     }
