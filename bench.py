@@ -70,6 +70,71 @@ def cpu_baseline(base, n_pairs):
             "pairs_per_s": n_pairs / dt, "seconds": dt}
 
 
+def serve_bench(torch, ff, n_req, lanes, budget):
+    """Config 3: a stream of mixed-size requests served (continuous batching
+    over `lanes` concurrent cohorts) vs plain (each request in turn through
+    ff_match_pair, FIFO).  Arrivals are Poisson at 0.7 x the plain path's
+    measured service rate, plus an all-at-once burst.  Latency = completion
+    seen by the host - arrival."""
+    import numpy as np
+    from paper_1805_03517_amd import synth
+    reqs, pool = synth.config3_requests(seed=3, n=n_req, per_kind=2)
+    dev = {k: (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for k, (a, b) in pool.items()}
+    m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
+                   hbm_budget=budget)
+    outs = [m._outputs(r["size"][1], r["size"][0], True, True) for r in reqs]
+    px = sum(r["size"][0] * r["size"][1] for r in reqs)
+    # warm both paths
+    for r, o in list(zip(reqs, outs))[:8]:
+        m.match(*dev[r["pool_key"]], out=o)
+    torch.cuda.synchronize()
+    m.serve_config(lanes=lanes, lane_bytes=budget // lanes)
+
+    def plain(arr):
+        lat = []
+        t0 = time.perf_counter()
+        for r, o, a in zip(reqs, outs, arr):
+            while time.perf_counter() - t0 < a:
+                pass
+            m.match(*dev[r["pool_key"]], out=o)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0 - a)
+        return lat, time.perf_counter() - t0
+
+    def served(arr):
+        lat = [None] * len(reqs)
+        t0 = time.perf_counter()
+        nxt = 0
+        left = len(reqs)
+        while left:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arr[nxt] <= now:
+                m.submit(*dev[reqs[nxt]["pool_key"]], tag=nxt, out=outs[nxt])
+                nxt += 1
+            for t in m.poll():
+                lat[t] = time.perf_counter() - t0 - arr[t]
+                left -= 1
+        return lat, time.perf_counter() - t0
+
+    def summary(lat, span):
+        lat = np.asarray(lat) * 1000.0
+        return {"pairs_per_s": len(lat) / span, "px_per_s": px / span,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+
+    burst = [0.0] * len(reqs)
+    lat, span = plain(burst)
+    mu = len(reqs) / span
+    rate = 0.7 * mu
+    arr = list(np.cumsum([r["unit_gap"] for r in reqs]) / rate)
+    out = {"requests": len(reqs), "sizes": [list(s) for s in synth.SERVE_SIZES], "lanes": lanes,
+           "hbm_budget": budget, "plain_service_rate": mu, "arrival_rate": rate,
+           "burst": {"plain": summary(lat, span)}}
+    out["burst"]["served"] = summary(*served(burst))
+    out["poisson"] = {"plain": summary(*plain(arr)), "served": summary(*served(arr))}
+    m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +145,9 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time per-pair ff_match_pair calls")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default line-kernel schedule")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
@@ -113,6 +181,13 @@ def main():
     for _ in range(args.warmup):
         m.match_batch(pairs, outs=outs)
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_tune:
+        print("[bench] autotuning the line-kernel schedule on this batch", file=sys.stderr, flush=True)
+        tuning = m.autotune(pairs, outs=outs)
+        for _ in range(2):
+            m.match_batch(pairs, outs=outs)
+        torch.cuda.synchronize()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -161,6 +236,11 @@ def main():
         dtp = time.perf_counter() - t0
         plain = {"pairs_per_s": args.batch * max(1, args.steps // 4) / dtp}
 
+    serving = None
+    if not args.no_serve:
+        print(f"[bench] serving: {args.serve_requests} mixed requests, served vs plain", file=sys.stderr, flush=True)
+        serving = serve_bench(torch, ff, args.serve_requests, lanes=4, budget=64 << 30)
+
     cpu = None
     if not args.no_cpu:
         print(f"[bench] oracle on {args.cpu_pairs} pairs (cpu baseline)", file=sys.stderr, flush=True)
@@ -184,13 +264,14 @@ def main():
         "config": {"workload": "KITTI-shaped 1242x375 RGB pairs (planar expansion up to 150 px, 4 boxes), "
                                f"4 levels, stride 3, 2 iterations, R 16, eps 1; {args.batch} pairs per "
                                f"step ({args.distinct} distinct)",
-                   "global_batch": args.batch, "parallelism": "none (1 GPU)",
+                   "global_batch": args.batch, "parallelism": "none (1 GPU)", "schedule": tuning,
                    "consistent_fraction": consistent},
         "roofline": {"bound": "hbm", "kernel": "col_phase", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": avg_bytes},
         "kernels": kernels,
         "plain": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -104,6 +104,48 @@ const char* ff_last_error(ff_handle h);
 /* Bytes of device workspace a batch of these pairs needs (no allocation). */
 uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
 
+/* ---- serving: continuous batching --------------------------------------
+ * The handle keeps `lanes` concurrent cohorts, each on its own HIP stream
+ * with its own preallocated workspace of `lane_bytes` bytes (lanes x
+ * lane_bytes must fit params.hbm_budget when a budget is set).  ff_submit
+ * queues one pair (FIFO) and returns at once; whenever a lane is idle, the
+ * queued pairs at the head that fit its workspace start as one grouped
+ * batch on that lane, overlapping with the cohorts running on the others.
+ * A pair's outputs are bit-identical to ff_match_pair on the same inputs,
+ * whatever cohort it ran in.  The inputs are read after the work the caller
+ * enqueued on `stream` before the submit; the caller keeps every buffer of
+ * the pair alive until ff_poll has returned its tag, after which the
+ * outputs are complete.  ff_match_pair / ff_match_batch on the same handle
+ * use a separate workspace.
+ *
+ * ff_serve_config: (re)configure; FF_ERR_BUSY while requests are queued or
+ *   running.  Without it the first ff_submit configures 4 lanes of
+ *   hbm_budget / 4 bytes (4 GiB each when no budget is set).
+ * ff_submit: FF_ERR_BUDGET when the pair alone exceeds lane_bytes.
+ * ff_poll: non-blocking; writes up to `max` finished tags (completion
+ *   order), returns how many, or -1 on error.
+ * ff_serve_inflight: queued + running pairs, or -1.                        */
+ff_status ff_serve_config(ff_handle h, int32_t lanes, uint64_t lane_bytes);
+ff_status ff_submit(ff_handle h, const ff_pair* pair, uint64_t tag, void* stream);
+int32_t   ff_poll(ff_handle h, uint64_t* tags_done, int32_t max);
+int32_t   ff_serve_inflight(ff_handle h);
+
+/* ---- schedule autotuning -----------------------------------------------
+ * The row and column phases run one wave per image line and solve each
+ * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves.  Both
+ * are scheduling choices only: the sweep's result is the same for every
+ * window size, so no choice changes any output.  ff_autotune runs this
+ * batch once per candidate (chunks, lines) in {2,4,8} x {2,4,8} (twice, the
+ * second timed with events) and keeps, per phase and level, the fastest;
+ * it synchronises the stream.  ff_tune_get writes 4 * levels int32
+ * (cfg[(phase * levels + level) * 2 + {0: chunks, 1: lines}], phase 0 = row,
+ * 1 = column) and returns that count, or -1 if max is too small;
+ * ff_tune_set installs such a vector (each entry 2, 4 or 8).  The default
+ * is chunks = 4, lines = 4 everywhere.                                    */
+ff_status ff_autotune(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
+int32_t   ff_tune_get(ff_handle h, int32_t* cfg, int32_t max);
+ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n);
+
 /* ---- per-kernel timing (tracing) ------------------------------------------
  * When enabled, every launch the handle enqueues is bracketed by a pair of
  * HIP events on the launch stream.  ff_profile_read synchronises those

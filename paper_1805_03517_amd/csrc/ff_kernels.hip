@@ -440,10 +440,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // window partition, so every lane re-reads exactly what it wrote.
 // upto (for intermediate captures): row 1 = LR, 2 = +RL, 3 = +RS0;
 // col 4 = TB, 5 = +RS1, 6 = +BT, 7 = +RS2.
-// grid (ceil(lines / 4), 2 * pairs), 256 threads.
-template <int RC, bool COL, int CH>
-__global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ pairs, int level, int iter,
-                                                    int upto, SearchConst sc)
+// WPB lines (waves) per block; grid (ceil(lines / WPB), 2 * pairs).  CH and
+// WPB only change scheduling, never the result.
+template <int RC, bool COL, int CH, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
+                                                         int iter, int upto, SearchConst sc)
 {
     const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int pd = lb / gridDim.x, bx = lb % gridDim.x;
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(256) void k_line_phase(const PairDev* __restrict__ 
     const int W = L.W, H = L.H;
     const int len = COL ? H : W, nlines = COL ? W : H;
     const int lane = threadIdx.x & 63;
-    const int line = bx * 4 + (threadIdx.x >> 6);
+    const int line = bx * WPB + (threadIdx.x >> 6);
     if (line >= nlines) return;
     gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
     gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
@@ -653,25 +654,41 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
 {
     hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
 }
-void launch_row_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
-                      int maxH, hipStream_t st)
+template <int RC, bool COL, int CH, int WPB>
+void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
+                   hipStream_t st)
 {
-    constexpr int CH = 4;
-    const dim3 grid((maxH + 3) / 4, 2 * npairs);
-    if (sc.radius == 16)
-        hipLaunchKernelGGL((k_line_phase<16, false, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
-    else
-        hipLaunchKernelGGL((k_line_phase<0, false, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
+                       dim3(64 * WPB), 0, st, d, level, iter, upto, sc);
 }
-void launch_col_phase(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc,
-                      int maxW, hipStream_t st)
+
+template <int RC, bool COL>
+bool launch_line_rc(int ch, int wpb, const PairDev* d, int npairs, int level, int iter, int upto,
+                    const SearchConst& sc, int nlines, hipStream_t st)
 {
-    constexpr int CH = 4;
-    const dim3 grid((maxW + 3) / 4, 2 * npairs);
+#define FF_LINE_CASE(C, B)                                                                    \
+    if (ch == C && wpb == B) {                                                                \
+        launch_line_t<RC, COL, C, B>(d, npairs, level, iter, upto, sc, nlines, st);          \
+        return true;                                                                          \
+    }
+    FF_LINE_CASE(2, 2) FF_LINE_CASE(2, 4) FF_LINE_CASE(2, 8)
+    FF_LINE_CASE(4, 2) FF_LINE_CASE(4, 4) FF_LINE_CASE(4, 8)
+    FF_LINE_CASE(8, 2) FF_LINE_CASE(8, 4) FF_LINE_CASE(8, 8)
+#undef FF_LINE_CASE
+    return false;
+}
+
+// One row or column phase of every pair and direction at one level.  ch =
+// chunks of 64 px per relaxation window, wpb = lines per block; both in
+// {2, 4, 8}.  Returns false for an unsupported (ch, wpb).
+bool launch_line_phase(bool col, int ch, int wpb, const PairDev* d, int npairs, int level, int iter, int upto,
+                       const SearchConst& sc, int nlines, hipStream_t st)
+{
     if (sc.radius == 16)
-        hipLaunchKernelGGL((k_line_phase<16, true, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
-    else
-        hipLaunchKernelGGL((k_line_phase<0, true, CH>), grid, dim3(256), 0, st, d, level, iter, upto, sc);
+        return col ? launch_line_rc<16, true>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st)
+                   : launch_line_rc<16, false>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st);
+    return col ? launch_line_rc<0, true>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st)
+               : launch_line_rc<0, false>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st);
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

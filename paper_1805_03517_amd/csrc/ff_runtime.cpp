@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <deque>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -28,8 +30,7 @@ void launch_desc(const PairDev*, int, int, int, int, hipStream_t);
 void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, hipStream_t);
-void launch_row_phase(const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
-void launch_col_phase(const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
+bool launch_line_phase(bool, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
@@ -46,15 +47,67 @@ struct ff_ctx {
     size_t arena_bytes = 0;
     PairDev* d_table = nullptr;      // device copy of the per-pair table
     size_t d_table_cap = 0;          // entries
-    PairDev* h_table = nullptr;      // pinned staging for the upload
-    size_t h_table_cap = 0;
-    hipEvent_t table_ev = nullptr;   // last upload from h_table finished
+    // pinned staging ring for table uploads: the host refills slot k only
+    // after the copy that last read it has finished, so it can run several
+    // calls ahead of the device
+    static constexpr int kStaging = 4;
+    PairDev* h_table[kStaging] = {};
+    size_t h_table_cap[kStaging] = {};
+    hipEvent_t table_ev[kStaging] = {};
+    unsigned staging_next = 0;
+    // captured launch sequences, keyed by the batch's launch geometry
+    struct GraphEntry {
+        std::vector<long long> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
+    std::vector<std::vector<long long>> seen;   // geometries launched once, not yet captured
+    hipStream_t cap_stream = nullptr;
+    bool use_graphs = true;
     std::vector<PairDev> last;       // what d_table holds now
     // tracing: event pairs around every launch while enabled
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<int, size_t>> prof;   // (kernel id, first event index)
+    struct ProfRec {
+        int kernel, level;
+        size_t ev;                                // first of its two events
+    };
+    std::vector<ProfRec> prof;
+    struct ServeState* serve = nullptr;         // serving engine, created on first use
+    // line-kernel schedule per phase (0 row, 1 col) and level: chunks of 64 px
+    // per relaxation window and lines per block (set by ff_autotune / ff_tune_set)
+    int tune_ch[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
+    int tune_wpb[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
+};
+
+// Serving: continuous batching over `lanes` concurrent cohorts.  Each lane
+// owns a stream, a completion event and a sub-context (its own arena and
+// pair table).  Submitted requests wait in a FIFO; whenever a lane is idle
+// the requests at the head of the FIFO that fit the lane's arena form a
+// cohort and run as one grouped batch on that lane's stream, overlapping
+// with the cohorts already running on the other lanes.
+struct ServeReq {
+    ff_pair pair;
+    uint64_t tag;
+    size_t bytes;
+    hipEvent_t ready;                // recorded on the submitter's stream
+};
+struct ServeLane {
+    ff_ctx* exec = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<uint64_t> tags;
+};
+struct ServeState {
+    std::vector<ServeLane> lanes;
+    size_t lane_bytes = 0;
+    int max_cohort = 0;
+    std::deque<ServeReq> pending;
+    std::deque<uint64_t> done;
+    std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
@@ -137,7 +190,7 @@ ff_status validate_pair(ff_ctx* h, const ff_pair& q)
     return FF_OK;
 }
 
-ff_status ensure_arena(ff_ctx* h, size_t need)
+ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
 {
     if (h->prm.hbm_budget && need > h->prm.hbm_budget) {
         char buf[160];
@@ -153,7 +206,7 @@ ff_status ensure_arena(ff_ctx* h, size_t need)
         h->arena_bytes = 0;
         h->last.clear();
     }
-    const size_t want = need + need / 8;     // head-room against regrowth
+    const size_t want = exact ? need : need + need / 8;     // head-room against regrowth
     hipError_t e = hipMalloc(&h->arena, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -229,20 +282,18 @@ ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t s
         FF_HIP(h, hipMalloc((void**)&h->d_table, cap * sizeof(PairDev)));
         h->d_table_cap = cap;
     }
-    if (n > h->h_table_cap) {
-        if (h->h_table) {
-            FF_HIP(h, hipEventSynchronize(h->table_ev));
-            FF_HIP(h, hipHostFree(h->h_table));
-            h->h_table = nullptr;
-        }
+    const int k = (int)(h->staging_next++ % ff_ctx::kStaging);
+    FF_HIP(h, hipEventSynchronize(h->table_ev[k]));   // the copy that last read slot k is done
+    if (n > h->h_table_cap[k]) {
+        if (h->h_table[k]) FF_HIP(h, hipHostFree(h->h_table[k]));
+        h->h_table[k] = nullptr;
         const size_t cap = std::max<size_t>(n, 16);
-        FF_HIP(h, hipHostMalloc((void**)&h->h_table, cap * sizeof(PairDev), hipHostMallocDefault));
-        h->h_table_cap = cap;
+        FF_HIP(h, hipHostMalloc((void**)&h->h_table[k], cap * sizeof(PairDev), hipHostMallocDefault));
+        h->h_table_cap[k] = cap;
     }
-    FF_HIP(h, hipEventSynchronize(h->table_ev));      // previous upload done reading h_table
-    std::memcpy(h->h_table, tab.data(), n * sizeof(PairDev));
-    FF_HIP(h, hipMemcpyAsync(h->d_table, h->h_table, n * sizeof(PairDev), hipMemcpyHostToDevice, st));
-    FF_HIP(h, hipEventRecord(h->table_ev, st));
+    std::memcpy(h->h_table[k], tab.data(), n * sizeof(PairDev));
+    FF_HIP(h, hipMemcpyAsync(h->d_table, h->h_table[k], n * sizeof(PairDev), hipMemcpyHostToDevice, st));
+    FF_HIP(h, hipEventRecord(h->table_ev[k], st));
     h->last = tab;
     return FF_OK;
 }
@@ -274,7 +325,7 @@ const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "se
 enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
-long prof_begin(ff_ctx* h, int kernel, hipStream_t st)
+long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
 {
     if (!h->prof_on) return -1;
     while (h->ev_used + 2 > h->ev_pool.size()) {
@@ -285,7 +336,7 @@ long prof_begin(ff_ctx* h, int kernel, hipStream_t st)
     const size_t i = h->ev_used;
     h->ev_used += 2;
     (void)hipEventRecord(h->ev_pool[i], st);
-    h->prof.emplace_back(kernel, i);
+    h->prof.push_back(ff_ctx::ProfRec{kernel, level, i});
     return (long)i;
 }
 
@@ -294,14 +345,150 @@ void prof_end(ff_ctx* h, long i, hipStream_t st)
     if (i >= 0) (void)hipEventRecord(h->ev_pool[(size_t)i + 1], st);
 }
 
-#define FF_TRACED(kernel, call)                 \
+#define FF_TRACED(kernel, level, call)          \
     do {                                        \
-        const long pi_ = prof_begin(h, kernel, st); \
+        const long pi_ = prof_begin(h, kernel, level, st); \
         call;                                   \
         prof_end(h, pi_, st);                   \
     } while (0)
 
 // Enqueue the whole search (or, for a debug stop, the part up to it).
+// Launch geometry of one batch: the largest level sizes over its pairs.
+struct Dims {
+    int n = 0;
+    int maxW[kMaxLevels] = {0}, maxH[kMaxLevels] = {0}, maxPx[kMaxLevels] = {0};
+    int maxQ = 0;
+};
+
+// Enqueue the launch sequence on `st`.  With an active stop, enqueue only up
+// to that point and copy the intermediate of pair 0 (tab0 / plan0).
+ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, const Stop& stop,
+                  const PairDev* tab0, const PairPlan* plan0)
+{
+    const ff_params& p = h->prm;
+    const int n = D.n;
+    const int L = p.levels, c = L - 1;
+    const SearchConst sc = search_const(p);
+    auto level_px = [&](int l) { return (size_t)plan0->W[l] * plan0->H[l]; };
+
+    FF_TRACED(KN_GRAY, 0, launch_gray(d, n, D.maxPx[0], st));
+    if (stop.active && stop.st.kind == FF_STAGE_GRAY) {
+        FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].gray[stop.st.image], level_px(0), hipMemcpyDeviceToDevice, st));
+        return FF_OK;
+    }
+    for (int l = 1; l < L; ++l) FF_TRACED(KN_DOWN2, l, launch_down2(d, n, l, D.maxPx[l], st));
+    if (stop.active && stop.st.kind == FF_STAGE_PYRAMID) {
+        const int l = stop.st.level;
+        FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].gray[stop.st.image], level_px(l), hipMemcpyDeviceToDevice, st));
+        return FF_OK;
+    }
+    for (int l = 0; l < L; ++l) FF_TRACED(KN_DESC, l, launch_desc(d, n, l, D.maxW[l], D.maxH[l], st));
+    if (stop.active && stop.st.kind == FF_STAGE_DESC) {
+        const int l = stop.st.level;
+        launch_copy_desc_signed(tab0->lv[l].desc[stop.st.image], (int8_t*)stop.dst, level_px(l) * 16, st);
+        return FF_OK;
+    }
+    FF_TRACED(KN_SEED_REC, c, launch_seed_records(d, n, c, D.maxPx[c], st));
+    FF_TRACED(KN_SEED_NN, c, launch_seed_nn(d, n, c, p.seed_stride, D.maxQ, D.maxPx[c], st));
+    if (stop.active && stop.st.kind == FF_STAGE_SEEDS) {
+        launch_keys_to_index(tab0->keys[stop.st.dir], (int32_t*)stop.dst, plan0->nsx * plan0->nsy, st);
+        return FF_OK;
+    }
+    for (int l = c; l >= 0; --l) {
+        FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, D.maxPx[l], st));
+        const bool stop_here = stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
+        if (stop_here && stop.st.step == 0) {
+            FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
+            return FF_OK;
+        }
+        for (int t = 0; t < p.iters; ++t) {
+            const bool last = stop_here && stop.st.iter == t;
+            const int upto = last ? stop.st.step : 7;
+            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], d, n, l, t,
+                                                std::min(upto, 3), sc, D.maxH[l], st));
+            if (upto >= 4) {
+                FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 1, D.maxW[l], D.maxH[l], st));
+                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], d, n, l, t, upto, sc,
+                                                    D.maxW[l], st));
+                FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
+            }
+            if (last) {
+                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8,
+                                         hipMemcpyDeviceToDevice, st));
+                return FF_OK;
+            }
+        }
+    }
+    if (stop.active) return fail(h, FF_ERR_INVALID, "debug stage names a point the schedule does not reach");
+    FF_TRACED(KN_FB, 0, launch_fb(d, n, sc.eps2, D.maxPx[0], st));
+    return FF_OK;
+}
+
+constexpr size_t kMaxGraphs = 16;
+
+// Replay the captured launch sequence for this geometry.  A geometry seen
+// for the first time is launched directly; the second time it is captured
+// on the handle's private stream.  The per-pair table is device memory
+// uploaded before the replay, so one graph serves every batch of the same
+// geometry whatever its buffers.
+ff_status launch_graph(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st)
+{
+    std::vector<long long> key;
+    key.push_back(D.n);
+    key.push_back((long long)(uintptr_t)d);
+    key.push_back(D.maxQ);
+    for (int l = 0; l < h->prm.levels; ++l) {
+        key.push_back(D.maxW[l]);
+        key.push_back(D.maxH[l]);
+        key.push_back(D.maxPx[l]);
+    }
+    for (size_t i = 0; i < h->graphs.size(); ++i) {
+        if (h->graphs[i].key != key) continue;
+        ff_ctx::GraphEntry e = h->graphs[i];
+        h->graphs.erase(h->graphs.begin() + (long)i);
+        h->graphs.push_back(e);                        // most recently used last
+        FF_HIP(h, hipGraphLaunch(e.exec, st));
+        return FF_OK;
+    }
+    auto it = std::find(h->seen.begin(), h->seen.end(), key);
+    if (it == h->seen.end()) {
+        if (h->seen.size() >= 64) h->seen.erase(h->seen.begin());
+        h->seen.push_back(key);
+        return enqueue(h, d, D, st, Stop{}, nullptr, nullptr);
+    }
+    h->seen.erase(it);
+    if (!h->cap_stream) FF_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    FF_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    ff_status s = enqueue(h, d, D, h->cap_stream, Stop{}, nullptr, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+    if (s != FF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (ec != hipSuccess) return hip_fail(h, ec, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(h, ei, "hipGraphInstantiate");
+    }
+    if (h->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(h->graphs.front().exec);
+        (void)hipGraphDestroy(h->graphs.front().graph);
+        h->graphs.erase(h->graphs.begin());
+    }
+    ff_ctx::GraphEntry e;
+    e.key = key;
+    e.graph = g;
+    e.exec = ex;
+    h->graphs.push_back(e);
+    FF_HIP(h, hipGraphLaunch(ex, st));
+    return FF_OK;
+}
+
+// Validate, size the workspace, upload the pair table, then enqueue the
+// search (graph replay unless tracing or stopping at an intermediate).
 ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop& stop)
 {
     if (n < 1 || n > 32767) return fail(h, FF_ERR_INVALID, "batch size must be in 1..32767");
@@ -321,74 +508,261 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     build_table(h, pairs, n, tab, plans);
     s = upload_table(h, tab, st);
     if (s != FF_OK) return s;
-    const PairDev* d = h->d_table;
 
-    int maxW[kMaxLevels] = {0}, maxH[kMaxLevels] = {0}, maxPx[kMaxLevels] = {0};
-    int maxQ = 0;
+    Dims D;
+    D.n = n;
     for (int i = 0; i < n; ++i) {
         for (int l = 0; l < p.levels; ++l) {
-            maxW[l] = std::max(maxW[l], plans[i].W[l]);
-            maxH[l] = std::max(maxH[l], plans[i].H[l]);
-            maxPx[l] = std::max(maxPx[l], plans[i].W[l] * plans[i].H[l]);
+            D.maxW[l] = std::max(D.maxW[l], plans[i].W[l]);
+            D.maxH[l] = std::max(D.maxH[l], plans[i].H[l]);
+            D.maxPx[l] = std::max(D.maxPx[l], plans[i].W[l] * plans[i].H[l]);
         }
-        maxQ = std::max(maxQ, plans[i].nsx * plans[i].nsy);
+        D.maxQ = std::max(D.maxQ, plans[i].nsx * plans[i].nsy);
     }
-    const int L = p.levels, c = L - 1;
-    const SearchConst sc = search_const(p);
-
-    FF_TRACED(KN_GRAY, launch_gray(d, n, maxPx[0], st));
-    if (stop.active && stop.st.kind == FF_STAGE_GRAY) {
-        FF_HIP(h, hipMemcpyAsync(stop.dst, tab[0].lv[0].gray[stop.st.image], (size_t)plans[0].W[0] * plans[0].H[0],
-                                 hipMemcpyDeviceToDevice, st));
-        return FF_OK;
-    }
-    for (int l = 1; l < L; ++l) FF_TRACED(KN_DOWN2, launch_down2(d, n, l, maxPx[l], st));
-    if (stop.active && stop.st.kind == FF_STAGE_PYRAMID) {
-        const int l = stop.st.level;
-        FF_HIP(h, hipMemcpyAsync(stop.dst, tab[0].lv[l].gray[stop.st.image], (size_t)plans[0].W[l] * plans[0].H[l],
-                                 hipMemcpyDeviceToDevice, st));
-        return FF_OK;
-    }
-    for (int l = 0; l < L; ++l) FF_TRACED(KN_DESC, launch_desc(d, n, l, maxW[l], maxH[l], st));
-    if (stop.active && stop.st.kind == FF_STAGE_DESC) {
-        const int l = stop.st.level;
-        launch_copy_desc_signed(tab[0].lv[l].desc[stop.st.image], (int8_t*)stop.dst,
-                                (size_t)plans[0].W[l] * plans[0].H[l] * 16, st);
-        return FF_OK;
-    }
-    FF_TRACED(KN_SEED_REC, launch_seed_records(d, n, c, maxPx[c], st));
-    FF_TRACED(KN_SEED_NN, launch_seed_nn(d, n, c, p.seed_stride, maxQ, maxPx[c], st));
-    if (stop.active && stop.st.kind == FF_STAGE_SEEDS) {
-        launch_keys_to_index(tab[0].keys[stop.st.dir], (int32_t*)stop.dst, plans[0].nsx * plans[0].nsy, st);
-        return FF_OK;
-    }
-    for (int l = c; l >= 0; --l) {
-        FF_TRACED(KN_INIT, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, maxPx[l], st));
-        const bool stop_here = stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
-        if (stop_here && stop.st.step == 0) {
-            FF_HIP(h, hipMemcpyAsync(stop.dst, tab[0].lv[l].state[stop.st.dir], (size_t)plans[0].W[l] * plans[0].H[l] * 8,
-                                     hipMemcpyDeviceToDevice, st));
-            return FF_OK;
-        }
-        for (int t = 0; t < p.iters; ++t) {
-            const bool last = stop_here && stop.st.iter == t;
-            const int upto = last ? stop.st.step : 7;
-            FF_TRACED(KN_ROW, launch_row_phase(d, n, l, t, std::min(upto, 3), sc, maxH[l], st));
-            if (upto >= 4) {
-                FF_TRACED(KN_TRANS, launch_transpose_state(d, n, l, 1, maxW[l], maxH[l], st));
-                FF_TRACED(KN_COL, launch_col_phase(d, n, l, t, upto, sc, maxW[l], st));
-                FF_TRACED(KN_TRANS, launch_transpose_state(d, n, l, 0, maxW[l], maxH[l], st));
-            }
-            if (last) {
-                FF_HIP(h, hipMemcpyAsync(stop.dst, tab[0].lv[l].state[stop.st.dir],
-                                         (size_t)plans[0].W[l] * plans[0].H[l] * 8, hipMemcpyDeviceToDevice, st));
-                return FF_OK;
-            }
-        }
-    }
-    if (stop.active) return fail(h, FF_ERR_INVALID, "debug stage names a point the schedule does not reach");
-    FF_TRACED(KN_FB, launch_fb(d, n, sc.eps2, maxPx[0], st));
+    if (!stop.active && !h->prof_on && h->use_graphs)
+        s = launch_graph(h, h->d_table, D, st);
+    else
+        s = enqueue(h, h->d_table, D, st, stop, &tab[0], &plans[0]);
+    if (s != FF_OK) return s;
     FF_HIP(h, hipGetLastError());
+    return FF_OK;
+}
+
+struct Timed {
+    int kernel, level;
+    double ms;
+};
+
+// Synchronise the traced launches' events and turn them into durations.
+ff_status collect_profile(ff_ctx* h, std::vector<Timed>& out)
+{
+    for (const ff_ctx::ProfRec& r : h->prof) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(h->ev_pool[r.ev + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, h->ev_pool[r.ev], h->ev_pool[r.ev + 1]);
+        if (e != hipSuccess) {
+            h->prof.clear();
+            h->ev_used = 0;
+            return hip_fail(h, e, "event timing");
+        }
+        out.push_back(Timed{r.kernel, r.level, (double)t});
+    }
+    h->prof.clear();
+    h->ev_used = 0;
+    return FF_OK;
+}
+
+void drop_graphs(ff_ctx* h)
+{
+    for (auto& e : h->graphs) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+    }
+    h->graphs.clear();
+    h->seen.clear();
+}
+
+// Time every (chunks per window, lines per block) candidate on this batch
+// and keep, per phase and level, the fastest.  Each candidate runs twice;
+// the second run is timed.  The search result is the same for every
+// candidate, so tuning never changes an output.
+ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
+{
+    static const int kCand[][2] = {{2, 2}, {2, 4}, {2, 8}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}};
+    const int L = h->prm.levels;
+    double best[2][kMaxLevels];
+    int bch[2][kMaxLevels], bwpb[2][kMaxLevels];
+    for (int ph = 0; ph < 2; ++ph)
+        for (int l = 0; l < L; ++l) {
+            best[ph][l] = 1e30;
+            bch[ph][l] = h->tune_ch[ph][l];
+            bwpb[ph][l] = h->tune_wpb[ph][l];
+        }
+    const bool was_on = h->prof_on;
+    std::vector<Timed> discard;
+    (void)collect_profile(h, discard);
+    for (const auto& c : kCand) {
+        drop_graphs(h);
+        for (int ph = 0; ph < 2; ++ph)
+            for (int l = 0; l < L; ++l) {
+                h->tune_ch[ph][l] = c[0];
+                h->tune_wpb[ph][l] = c[1];
+            }
+        for (int rep = 0; rep < 2; ++rep) {
+            h->prof_on = rep == 1;
+            ff_status s = run(h, pairs, n, st, Stop{});
+            h->prof_on = false;
+            if (s != FF_OK) {
+                h->prof_on = was_on;
+                return s;
+            }
+        }
+        std::vector<Timed> recs;
+        ff_status s = collect_profile(h, recs);
+        if (s != FF_OK) {
+            h->prof_on = was_on;
+            return s;
+        }
+        double t[2][kMaxLevels] = {{0}};
+        for (const Timed& r : recs) {
+            if (r.kernel == KN_ROW) t[0][r.level] += r.ms;
+            if (r.kernel == KN_COL) t[1][r.level] += r.ms;
+        }
+        for (int ph = 0; ph < 2; ++ph)
+            for (int l = 0; l < L; ++l)
+                if (t[ph][l] < best[ph][l]) {
+                    best[ph][l] = t[ph][l];
+                    bch[ph][l] = c[0];
+                    bwpb[ph][l] = c[1];
+                }
+    }
+    for (int ph = 0; ph < 2; ++ph)
+        for (int l = 0; l < L; ++l) {
+            h->tune_ch[ph][l] = bch[ph][l];
+            h->tune_wpb[ph][l] = bwpb[ph][l];
+        }
+    h->prof_on = was_on;
+    drop_graphs(h);
+    return FF_OK;
+}
+
+ff_ctx* make_ctx(const ff_params& p, int device)
+{
+    ff_ctx* h = new ff_ctx;
+    h->prm = p;
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return nullptr;
+    }
+    for (int k = 0; k < ff_ctx::kStaging; ++k) {
+        if (hipEventCreateWithFlags(&h->table_ev[k], hipEventDisableTiming) != hipSuccess) {
+            for (int j = 0; j < k; ++j) (void)hipEventDestroy(h->table_ev[j]);
+            delete h;
+            return nullptr;
+        }
+    }
+    const char* g = std::getenv("FF_GRAPHS");
+    h->use_graphs = !(g && g[0] == '0');
+    return h;
+}
+
+void free_ctx(ff_ctx* h);
+
+void free_serve(ff_ctx* h)
+{
+    ServeState* sv = h->serve;
+    if (!sv) return;
+    for (ServeLane& l : sv->lanes) {
+        if (l.stream) (void)hipStreamSynchronize(l.stream);
+        if (l.done) (void)hipEventDestroy(l.done);
+        if (l.stream) (void)hipStreamDestroy(l.stream);
+        if (l.exec) free_ctx(l.exec);
+    }
+    for (const ServeReq& r : sv->pending) (void)hipEventDestroy(r.ready);
+    for (hipEvent_t e : sv->ev_pool) (void)hipEventDestroy(e);
+    delete sv;
+    h->serve = nullptr;
+}
+
+void free_ctx(ff_ctx* h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    free_serve(h);
+    (void)hipDeviceSynchronize();
+    if (h->arena) (void)hipFree(h->arena);
+    if (h->d_table) (void)hipFree(h->d_table);
+    for (int k = 0; k < ff_ctx::kStaging; ++k) {
+        if (h->h_table[k]) (void)hipHostFree(h->h_table[k]);
+        if (h->table_ev[k]) (void)hipEventDestroy(h->table_ev[k]);
+    }
+    for (auto& e : h->graphs) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+ff_status serve_configure(ff_ctx* h, int lanes, size_t lane_bytes)
+{
+    if (lanes < 1 || lanes > 16) return fail(h, FF_ERR_INVALID, "lanes must be in 1..16");
+    if (lane_bytes < (1u << 20)) return fail(h, FF_ERR_INVALID, "lane_bytes must be at least 1 MiB");
+    if (h->prm.hbm_budget && (uint64_t)lanes * lane_bytes > h->prm.hbm_budget)
+        return fail(h, FF_ERR_BUDGET, "lanes x lane_bytes exceeds the HBM budget");
+    if (h->serve) {
+        for (const ServeLane& l : h->serve->lanes)
+            if (l.busy) return fail(h, FF_ERR_BUSY, "serving engine has work in flight");
+        if (!h->serve->pending.empty()) return fail(h, FF_ERR_BUSY, "serving engine has queued requests");
+        free_serve(h);
+    }
+    FF_HIP(h, hipSetDevice(h->device));
+    ServeState* sv = new ServeState;
+    h->serve = sv;
+    sv->lane_bytes = lane_bytes;
+    sv->max_cohort = 32767;
+    sv->lanes.resize(lanes);
+    ff_params sub = h->prm;
+    sub.hbm_budget = 0;                       // the parent handle enforces the budget
+    for (ServeLane& l : sv->lanes) {
+        l.exec = make_ctx(sub, h->device);
+        if (!l.exec) {
+            free_serve(h);
+            return fail(h, FF_ERR_HIP, "lane context creation failed");
+        }
+        if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess) {
+            free_serve(h);
+            return fail(h, FF_ERR_HIP, "lane stream/event creation failed");
+        }
+        ff_status st = ensure_arena(l.exec, lane_bytes, true);
+        if (st != FF_OK) {
+            std::string msg = l.exec->err;
+            free_serve(h);
+            return fail(h, st, "lane arena: " + msg);
+        }
+    }
+    return FF_OK;
+}
+
+// Retire finished cohorts, then start new cohorts on idle lanes.
+ff_status serve_pump(ff_ctx* h)
+{
+    ServeState* sv = h->serve;
+    for (ServeLane& l : sv->lanes) {
+        if (!l.busy) continue;
+        const hipError_t q = hipEventQuery(l.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return hip_fail(h, q, "lane completion");
+        for (uint64_t t : l.tags) sv->done.push_back(t);
+        l.tags.clear();
+        l.busy = false;
+    }
+    for (ServeLane& l : sv->lanes) {
+        if (l.busy || sv->pending.empty()) continue;
+        std::vector<ff_pair> cohort;
+        size_t bytes = 0;
+        while (!sv->pending.empty() && (int)cohort.size() < sv->max_cohort &&
+               bytes + sv->pending.front().bytes <= sv->lane_bytes) {
+            ServeReq r = sv->pending.front();
+            sv->pending.pop_front();
+            FF_HIP(h, hipStreamWaitEvent(l.stream, r.ready, 0));
+            sv->ev_pool.push_back(r.ready);
+            cohort.push_back(r.pair);
+            l.tags.push_back(r.tag);
+            bytes += r.bytes;
+        }
+        if (cohort.empty()) break;
+        ff_status st = run(l.exec, cohort.data(), (int)cohort.size(), l.stream, Stop{});
+        if (st != FF_OK) {
+            l.tags.clear();
+            return fail(h, st, "cohort launch: " + l.exec->err);
+        }
+        FF_HIP(h, hipEventRecord(l.done, l.stream));
+        l.busy = true;
+    }
     return FF_OK;
 }
 
@@ -411,14 +785,8 @@ ff_status ff_create(const ff_params* params, int device, ff_handle* out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FF_ERR_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FF_ERR_UNSUPPORTED;
-    ff_ctx* h = new ff_ctx;
-    h->prm = *params;
-    h->device = device;
-    if (hipSetDevice(device) != hipSuccess ||
-        hipEventCreateWithFlags(&h->table_ev, hipEventDisableTiming) != hipSuccess) {
-        delete h;
-        return FF_ERR_HIP;
-    }
+    ff_ctx* h = make_ctx(*params, device);
+    if (!h) return FF_ERR_HIP;
     *out = h;
     return FF_OK;
 }
@@ -471,23 +839,14 @@ ff_status ff_profile_enable(ff_handle h, int32_t on)
 int32_t ff_profile_read(ff_handle h, ff_profile_entry* out, int32_t max)
 {
     if (!h || (!out && max > 0) || max < 0) return -1;
+    std::vector<Timed> recs;
+    if (collect_profile(h, recs) != FF_OK) return -1;
     int32_t launches[KN_COUNT] = {0};
     double ms[KN_COUNT] = {0};
-    for (const auto& r : h->prof) {
-        float t = 0.f;
-        if (hipEventSynchronize(h->ev_pool[r.second + 1]) != hipSuccess ||
-            hipEventElapsedTime(&t, h->ev_pool[r.second], h->ev_pool[r.second + 1]) != hipSuccess) {
-            (void)hipGetLastError();
-            h->prof.clear();
-            h->ev_used = 0;
-            fail(h, FF_ERR_HIP, "event timing failed");
-            return -1;
-        }
-        launches[r.first] += 1;
-        ms[r.first] += t;
+    for (const Timed& r : recs) {
+        launches[r.kernel] += 1;
+        ms[r.kernel] += r.ms;
     }
-    h->prof.clear();
-    h->ev_used = 0;
     int32_t k = 0;
     for (int i = 0; i < KN_COUNT; ++i) {
         if (!launches[i]) continue;
@@ -502,17 +861,100 @@ int32_t ff_profile_read(ff_handle h, ff_profile_entry* out, int32_t max)
     return std::min(k, max);
 }
 
+ff_status ff_autotune(ff_handle h, const ff_pair* pairs, int32_t n, void* stream)
+{
+    if (!h) return FF_ERR_INVALID;
+    if (!pairs || n < 1) return fail(h, FF_ERR_INVALID, "pairs is NULL or n < 1");
+    return autotune(h, pairs, n, (hipStream_t)stream);
+}
+
+int32_t ff_tune_get(ff_handle h, int32_t* cfg, int32_t max)
+{
+    const int L = h ? h->prm.levels : 0;
+    if (!h || max < 4 * L || !cfg) return -1;
+    for (int ph = 0; ph < 2; ++ph)
+        for (int l = 0; l < L; ++l) {
+            cfg[(ph * L + l) * 2 + 0] = h->tune_ch[ph][l];
+            cfg[(ph * L + l) * 2 + 1] = h->tune_wpb[ph][l];
+        }
+    return 4 * L;
+}
+
+ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n)
+{
+    if (!h) return FF_ERR_INVALID;
+    const int L = h->prm.levels;
+    if (!cfg || n != 4 * L) return fail(h, FF_ERR_INVALID, "tuning vector must hold 4 * levels entries");
+    for (int i = 0; i < n; ++i)
+        if (cfg[i] != 2 && cfg[i] != 4 && cfg[i] != 8)
+            return fail(h, FF_ERR_INVALID, "chunks per window and lines per block must be 2, 4 or 8");
+    for (int ph = 0; ph < 2; ++ph)
+        for (int l = 0; l < L; ++l) {
+            h->tune_ch[ph][l] = cfg[(ph * L + l) * 2 + 0];
+            h->tune_wpb[ph][l] = cfg[(ph * L + l) * 2 + 1];
+        }
+    drop_graphs(h);
+    return FF_OK;
+}
+
 void ff_destroy(ff_handle h)
 {
-    if (!h) return;
-    (void)hipSetDevice(h->device);
-    (void)hipDeviceSynchronize();
-    if (h->arena) (void)hipFree(h->arena);
-    if (h->d_table) (void)hipFree(h->d_table);
-    if (h->h_table) (void)hipHostFree(h->h_table);
-    if (h->table_ev) (void)hipEventDestroy(h->table_ev);
-    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-    delete h;
+    free_ctx(h);
+}
+
+ff_status ff_serve_config(ff_handle h, int32_t lanes, uint64_t lane_bytes)
+{
+    if (!h) return FF_ERR_INVALID;
+    return serve_configure(h, lanes, (size_t)lane_bytes);
+}
+
+ff_status ff_submit(ff_handle h, const ff_pair* pair, uint64_t tag, void* stream)
+{
+    if (!h) return FF_ERR_INVALID;
+    if (!pair) return fail(h, FF_ERR_INVALID, "pair is NULL");
+    if (!h->serve) {
+        const size_t lb = h->prm.hbm_budget ? (size_t)(h->prm.hbm_budget / 4) : ((size_t)4 << 30);
+        ff_status s = serve_configure(h, 4, lb);
+        if (s != FF_OK) return s;
+    }
+    ff_status s = validate_pair(h, *pair);
+    if (s != FF_OK) return s;
+    ServeState* sv = h->serve;
+    const size_t bytes = plan_pair(h->prm, pair->width, pair->height).bytes;
+    if (bytes > sv->lane_bytes) return fail(h, FF_ERR_BUDGET, "pair does not fit one serving lane's arena");
+    hipEvent_t ready;
+    if (!sv->ev_pool.empty()) {
+        ready = sv->ev_pool.back();
+        sv->ev_pool.pop_back();
+    } else {
+        FF_HIP(h, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    }
+    FF_HIP(h, hipEventRecord(ready, (hipStream_t)stream));
+    sv->pending.push_back(ServeReq{*pair, tag, bytes, ready});
+    return serve_pump(h);
+}
+
+int32_t ff_poll(ff_handle h, uint64_t* tags_done, int32_t max)
+{
+    if (!h || max < 0 || (max > 0 && !tags_done)) return -1;
+    if (!h->serve) return 0;
+    if (serve_pump(h) != FF_OK) return -1;
+    ServeState* sv = h->serve;
+    int32_t k = 0;
+    while (k < max && !sv->done.empty()) {
+        tags_done[k++] = sv->done.front();
+        sv->done.pop_front();
+    }
+    return k;
+}
+
+int32_t ff_serve_inflight(ff_handle h)
+{
+    if (!h) return -1;
+    if (!h->serve) return 0;
+    int32_t n = (int32_t)h->serve->pending.size();
+    for (const ServeLane& l : h->serve->lanes) n += (int32_t)l.tags.size();
+    return n;
 }
 
 const char* ff_last_error(ff_handle h)

@@ -19,7 +19,9 @@ INF = 2**31 - 1
 
 # Every symbol include/ff.h declares, in declaration order.
 EXPORTS = ("ff_create", "ff_match_pair", "ff_match_batch", "ff_destroy", "ff_last_error",
-           "ff_workspace_bytes", "ff_profile_enable", "ff_profile_read", "ff_debug_stage")
+           "ff_workspace_bytes", "ff_serve_config", "ff_submit", "ff_poll", "ff_serve_inflight",
+           "ff_autotune", "ff_tune_get", "ff_tune_set", "ff_profile_enable", "ff_profile_read",
+           "ff_debug_stage")
 
 
 class FFError(RuntimeError):
@@ -76,6 +78,20 @@ def lib():
         l.ff_last_error.restype = ctypes.c_char_p
         l.ff_workspace_bytes.argtypes = [vp, ctypes.POINTER(Pair), i32]
         l.ff_workspace_bytes.restype = ctypes.c_uint64
+        l.ff_serve_config.argtypes = [vp, i32, ctypes.c_uint64]
+        l.ff_serve_config.restype = ctypes.c_int
+        l.ff_submit.argtypes = [vp, ctypes.POINTER(Pair), ctypes.c_uint64, vp]
+        l.ff_submit.restype = ctypes.c_int
+        l.ff_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32]
+        l.ff_poll.restype = i32
+        l.ff_serve_inflight.argtypes = [vp]
+        l.ff_serve_inflight.restype = i32
+        l.ff_autotune.argtypes = [vp, ctypes.POINTER(Pair), i32, vp]
+        l.ff_autotune.restype = ctypes.c_int
+        l.ff_tune_get.argtypes = [vp, ctypes.POINTER(i32), i32]
+        l.ff_tune_get.restype = i32
+        l.ff_tune_set.argtypes = [vp, ctypes.POINTER(i32), i32]
+        l.ff_tune_set.restype = ctypes.c_int
         l.ff_profile_enable.argtypes = [vp, i32]
         l.ff_profile_enable.restype = ctypes.c_int
         l.ff_profile_read.argtypes = [vp, ctypes.POINTER(ProfileEntry), i32]
@@ -193,6 +209,59 @@ class Matcher:
                                          ctypes.c_void_p(dst.data_ptr()),
                                          _stream_ptr(self._torch, self.device)))
         return dst
+
+    # -- serving ----------------------------------------------------------
+    def serve_config(self, lanes=4, lane_bytes=4 << 30):
+        self._check(lib().ff_serve_config(self._h, lanes, lane_bytes))
+
+    def submit(self, img1, img2, tag, bwd=True, cost=True, out=None):
+        """Queue one pair; returns its output dict (complete once poll() has
+        returned ``tag``).  The tensors are kept alive until then."""
+        H, W = int(img1.shape[0]), int(img1.shape[1])
+        o = out if out is not None else self._outputs(H, W, bwd, cost)
+        p = self._pair(img1, img2, o)
+        if not hasattr(self, "_inflight"):
+            self._inflight = {}
+        self._inflight[int(tag)] = (img1, img2, o)
+        st = lib().ff_submit(self._h, ctypes.byref(p), int(tag), _stream_ptr(self._torch, self.device))
+        if st != FF_OK:
+            self._inflight.pop(int(tag), None)
+            self._check(st)
+        return o
+
+    def poll(self, max_tags=1024):
+        """Tags finished since the last poll (non-blocking)."""
+        buf = (ctypes.c_uint64 * max_tags)()
+        n = lib().ff_poll(self._h, buf, max_tags)
+        if n < 0:
+            self._check(FF_ERR_HIP)
+        tags = [int(buf[i]) for i in range(n)]
+        for t in tags:
+            getattr(self, "_inflight", {}).pop(t, None)
+        return tags
+
+    def inflight(self):
+        return int(lib().ff_serve_inflight(self._h))
+
+    # -- schedule tuning ----------------------------------------------------
+    def autotune(self, pairs, outs=None):
+        """Pick the line-kernel schedule per phase and level on this batch."""
+        outs = outs if outs is not None else [
+            self._outputs(int(a.shape[0]), int(a.shape[1])) for a, _ in pairs]
+        arr = (Pair * len(pairs))(*[self._pair(a, b, o) for (a, b), o in zip(pairs, outs)])
+        self._check(lib().ff_autotune(self._h, arr, len(pairs), _stream_ptr(self._torch, self.device)))
+        return self.tuning()
+
+    def tuning(self):
+        n = 4 * self.params.levels
+        buf = (ctypes.c_int32 * n)()
+        if lib().ff_tune_get(self._h, buf, n) != n:
+            self._check(FF_ERR_INVALID)
+        return [int(v) for v in buf]
+
+    def set_tuning(self, cfg):
+        buf = (ctypes.c_int32 * len(cfg))(*cfg)
+        self._check(lib().ff_tune_set(self._h, buf, len(cfg)))
 
     def profile(self, on: bool):
         """Bracket every launch with HIP events (per-kernel device time)."""

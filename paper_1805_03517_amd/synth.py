@@ -17,7 +17,7 @@ from scipy import ndimage
 
 __all__ = [
     "noise_texture", "translated_pair", "config0", "config1", "config2",
-    "config3_stream", "config4_batch", "SERVE_SIZES",
+    "config3_stream", "config3_requests", "config4_batch", "SERVE_SIZES",
 ]
 
 
@@ -80,10 +80,10 @@ def _road_texture(rng: np.random.Generator, h: int, w: int) -> np.ndarray:
         base = base + 60.0 * (yy - 0.5) * (1.0 if c == 2 else -0.6)
         out[..., c] = base
     for _ in range(80):
-        rw = int(rng.integers(8, 90))
-        rh = int(rng.integers(6, 60))
-        x0 = int(rng.integers(0, w - rw))
-        y0 = int(rng.integers(0, h - rh))
+        rw = min(int(rng.integers(8, 90)), max(1, w - 1))
+        rh = min(int(rng.integers(6, 60)), max(1, h - 1))
+        x0 = int(rng.integers(0, max(1, w - rw)))
+        y0 = int(rng.integers(0, max(1, h - rh)))
         col = rng.uniform(0, 255, size=3)
         alpha = rng.uniform(0.35, 0.8)
         out[y0:y0 + rh, x0:x0 + rw, :] = (1 - alpha) * out[y0:y0 + rh, x0:x0 + rw, :] + alpha * col
@@ -226,3 +226,30 @@ def config4_batch(seed: int = 4, n: int = 4096, lo: int = 96, hi: int = 256):
                                        rect_d=tuple(int(v) for v in rd))
         out.append((i1, i2, meta))
     return out
+
+
+def config3_requests(seed: int = 3, n: int = 256, per_kind: int = 2):
+    """Served-stream workload drawn like ``config3_stream`` but over a pool of
+    ``per_kind`` distinct pairs per (size, generator) so it builds quickly.
+
+    Returns (requests, pool): requests is a list of dicts {size, kind, pool_key,
+    unit_gap} (unit_gap = Exp(1) inter-arrival gap, scaled by 1/rate by the
+    caller); pool maps (w, h, kind, k) -> (img1, img2).
+    """
+    rng = np.random.default_rng(seed)
+    pool = {}
+    for (w, h) in SERVE_SIZES:
+        for kind in ("kitti", "sintel"):
+            for k in range(per_kind):
+                sub = np.random.default_rng([seed, w, h, 0 if kind == "kitti" else 1, k])
+                gen = _kitti_like if kind == "kitti" else _sintel_like
+                i1, i2, _ = gen(sub, w, h)
+                pool[(w, h, kind, k)] = (i1, i2)
+    reqs = []
+    for _ in range(n):
+        w, h = SERVE_SIZES[int(rng.integers(0, len(SERVE_SIZES)))]
+        kind = "kitti" if rng.integers(0, 2) == 0 else "sintel"
+        k = int(rng.integers(0, per_kind))
+        reqs.append({"size": (w, h), "kind": kind, "pool_key": (w, h, kind, k),
+                     "unit_gap": float(rng.exponential(1.0))})
+    return reqs, pool

@@ -278,3 +278,67 @@ def test_invalid_arguments_are_rejected(torch, ffm):
     assert e.value.status == ffm.FF_ERR_BUDGET
     m.close()
     tight.close()
+
+
+def test_graph_replays_match_direct_launches(torch, ffm, orc, monkeypatch):
+    """The second call with a geometry is captured into a hipGraph and later
+    calls replay it with a freshly uploaded pair table.  Every replay, with
+    eager work and synchronisation in between, must equal direct launches."""
+    monkeypatch.setenv("FF_GRAPHS", "0")
+    direct = ffm.Matcher(levels=3)
+    monkeypatch.setenv("FF_GRAPHS", "1")
+    graphed = ffm.Matcher(levels=3)
+    sets = []
+    for s in range(3):
+        pairs = [synth.translated_pair(np.random.default_rng([40, s, k]), 150 + 7 * k, 90 + 5 * k,
+                                       d=(k - 2, 3 - k))[:2] for k in range(4)]
+        sets.append([(_dev(torch, a), _dev(torch, b)) for a, b in pairs])
+    for rep in range(6):
+        dev = sets[rep % 3]
+        say("graph replay", rep)
+        g = graphed.match_batch(dev)
+        scratch = torch.randn(1 << 20, device="cuda").sum()       # eager work between replays
+        torch.cuda.synchronize()
+        r = direct.match_batch(dev)
+        torch.cuda.synchronize()
+        assert float(scratch) == float(scratch)
+        for o1, o2 in zip(g, r):
+            for key in o1:
+                assert torch.equal(o1[key], o2[key]), (rep, key)
+    # single pairs through ff_match_pair as well
+    a, b = sets[0][0]
+    for rep in range(4):
+        say("graph replay single pair", rep)
+        g = graphed.match(a, b)
+        r = direct.match(a, b)
+        torch.cuda.synchronize()
+        for key in g:
+            assert torch.equal(g[key], r[key])
+    direct.close()
+    graphed.close()
+
+
+def test_schedule_tuning_never_changes_output(torch, ffm, orc):
+    pairs = [synth.config1(seed=200)[:2], synth.config0()[:2], synth.config2(seed=201)[:2]]
+    pairs = [pairs[0], (np.stack([pairs[1][0]] * 3, -1), np.stack([pairs[1][1]] * 3, -1)), pairs[2]]
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b in pairs]
+    m = ffm.Matcher(levels=4)
+    say("default schedule")
+    ref = m.match_batch(dev)
+    torch.cuda.synchronize()
+    r0 = orc.match(pairs[1][0], pairs[1][1], orc.params(levels=4))
+    _compare_outputs(r0, ref[1], "default schedule vs oracle")
+    say("autotune")
+    cfg = m.autotune(dev)
+    assert len(cfg) == 16 and all(v in (2, 4, 8) for v in cfg)
+    for trial in [cfg, [2] * 16, [8] * 16, [2, 8] * 8, [8, 2] * 8]:
+        say("schedule", trial)
+        m.set_tuning(trial)
+        got = m.match_batch(dev)
+        torch.cuda.synchronize()
+        for o1, o2 in zip(ref, got):
+            for key in o1:
+                assert torch.equal(o1[key], o2[key]), (trial, key)
+    with pytest.raises(ffm.FFError):
+        m.set_tuning([3] * 16)
+    m.close()
