@@ -135,6 +135,46 @@ def serve_bench(torch, ff, n_req, lanes, budget):
     return out
 
 
+def c4_bench(torch, ff, n_pairs):
+    """Config 4: n uneven gray pairs (sides 96..256, translations up to
+    +-24 px, 3 levels) as ONE batched call (replayed hipGraph, tuned schedule)
+    vs one ff_match_pair call per pair; outputs compared bit for bit."""
+    from paper_1805_03517_amd import synth
+    pairs = synth.config4_batch(seed=4, n=n_pairs)
+    dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b, _ in pairs]
+    px = sum(a.shape[0] * a.shape[1] for a, _, _ in pairs)
+    mb = ff.Matcher(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
+    mp = ff.Matcher(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
+    ob = [mb._outputs(a.shape[0], a.shape[1]) for a, _ in dev]
+    op = [mp._outputs(a.shape[0], a.shape[1]) for a, _ in dev]
+    for _ in range(2):                          # second call captures the graph
+        mb.match_batch(dev, outs=ob)
+    tuning = mb.autotune(dev, outs=ob)
+    for _ in range(2):
+        mb.match_batch(dev, outs=ob)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mb.match_batch(dev, outs=ob)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    for (a, b), o in zip(dev, op):              # warm the per-pair path (graphs per shape)
+        mp.match(a, b, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (a, b), o in zip(dev, op):
+        mp.match(a, b, out=o)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = all(torch.equal(x[k], y[k]) for x, y in zip(ob, op) for k in x)
+    mb.close()
+    mp.close()
+    return {"pairs": n_pairs, "batched": {"pairs_per_s": n_pairs / tb, "px_per_s": px / tb, "ms": 1000 * tb},
+            "per_pair": {"pairs_per_s": n_pairs / tp, "px_per_s": px / tp, "ms": 1000 * tp},
+            "bit_identical": bool(same), "schedule": tuning}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +186,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time per-pair ff_match_pair calls")
     ap.add_argument("--no-tune", action="store_true", help="keep the default line-kernel schedule")
+    ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -241,6 +282,12 @@ def main():
         print(f"[bench] serving: {args.serve_requests} mixed requests, served vs plain", file=sys.stderr, flush=True)
         serving = serve_bench(torch, ff, args.serve_requests, lanes=4, budget=64 << 30)
 
+    batch_c4 = None
+    if args.c4_pairs:
+        print(f"[bench] config 4: {args.c4_pairs} uneven gray pairs, batched vs per-pair", file=sys.stderr,
+              flush=True)
+        batch_c4 = c4_bench(torch, ff, args.c4_pairs)
+
     cpu = None
     if not args.no_cpu:
         print(f"[bench] oracle on {args.cpu_pairs} pairs (cpu baseline)", file=sys.stderr, flush=True)
@@ -272,6 +319,7 @@ def main():
         "kernels": kernels,
         "plain": plain,
         "serving": serving,
+        "batch_c4": batch_c4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -342,3 +342,25 @@ def test_schedule_tuning_never_changes_output(torch, ffm, orc):
     with pytest.raises(ffm.FFError):
         m.set_tuning([3] * 16)
     m.close()
+
+
+def test_config4_style_batch_equals_per_pair(torch, ffm, orc):
+    """Uneven gray pairs (sides 96..256, translations up to 24 px) as one
+    batch equal per-pair calls bit for bit; three members against the oracle."""
+    pairs = synth.config4_batch(seed=4, n=96)
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b, _ in pairs]
+    mb = ffm.Matcher(levels=3)
+    mp = ffm.Matcher(levels=3)
+    say("config4-style batch of 96")
+    ob = mb.match_batch(dev)
+    ob = mb.match_batch(dev)          # graph capture on the repeated geometry
+    op = [mp.match(a, b) for a, b in dev]
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(ob, op)):
+        for key in x:
+            assert torch.equal(x[key], y[key]), (k, key)
+    for k in (0, 41, 95):
+        a, b, _ = pairs[k]
+        _compare_outputs(orc.match(a, b, orc.params(levels=3)), ob[k], f"config4 member {k}")
+    mb.close()
+    mp.close()
