@@ -27,6 +27,23 @@ sys.path.insert(0, ROOT)
 W0, H0, LEVELS = 1242, 375, 4
 HBM_PEAK_GBS = 8000.0
 
+# Line-kernel schedule for this workload as picked by ff_autotune on MI355X:
+# (chunks per window, lines per block) for row levels 0..3, then col levels 0..3.
+# Any schedule gives identical outputs; --autotune re-tunes on the spot.
+SCHEDULE_C1 = [4, 4, 2, 4, 2, 2, 2, 4, 2, 8, 4, 8, 2, 8, 2, 4]
+
+# HBM traffic of the col-phase kernel per launch (average over the 8
+# launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
+# Valid only for the kernel source it was measured on.
+TRAFFIC = {"kernel_sha": "fd463660d2acad61", "bytes_per_launch": 2646842832}
+
+
+def kernel_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1805_03517_amd", "csrc", "ff_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
 
 def level_dims(w, h, levels):
     out = []
@@ -135,6 +152,47 @@ def serve_bench(torch, ff, n_req, lanes, budget):
     return out
 
 
+I8_PEAK_TOPS = 5000.0      # MI355X dense i8 MFMA, 5.0 POP/s
+
+
+def seed_counts(w, h, levels, stride=3):
+    for _ in range(levels - 1):
+        w, h = w >> 1, h >> 1
+    q = -(-w // stride) * -(-h // stride)
+    return q, w * h
+
+
+def seednn_bench(torch, ff, pair, batch_prof):
+    """Seed search on i8 MFMA.  Useful ops = 2*Q*N*16 per direction (multiply
+    and add of the 16-deep dot products); the kernel issues 4x that (K = 64
+    MFMA holding [a, a, g] . [b, b, beta]).  Reported for the grouped launch of
+    the benchmark batch and for a large shape: one full-resolution 1242x375
+    level (levels = 1), Q = 51750 seeds x N = 465750 pixels, both directions."""
+    q, n = seed_counts(W0, H0, LEVELS)
+    launches, ms, nbatch = batch_prof
+    per_launch = nbatch * 2 * q * n * 16 * 2
+    grouped = {"useful_tops": per_launch / (ms / launches * 1e-3) / 1e12, "avg_us": 1000.0 * ms / launches}
+    grouped["issued_tops"] = 4 * grouped["useful_tops"]
+    m = ff.Matcher(levels=1, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
+    a, b = pair
+    for _ in range(2):
+        m.match(a, b)
+    torch.cuda.synchronize()
+    m.profile(True)
+    for _ in range(3):
+        m.match(a, b)
+    prof = m.profile_read()
+    m.close()
+    ql, nl = seed_counts(W0, H0, 1)
+    lw, lms = prof["seed_nn"]
+    useful = 2 * ql * nl * 16 * 2 / (lms / lw * 1e-3) / 1e12
+    large = {"Q": ql, "N": nl, "avg_us": 1000.0 * lms / lw, "useful_tops": useful, "issued_tops": 4 * useful}
+    for d in (grouped, large):
+        d["useful_frac"] = d["useful_tops"] / I8_PEAK_TOPS
+        d["issued_frac"] = d["issued_tops"] / I8_PEAK_TOPS
+    return {"peak_tops": I8_PEAK_TOPS, "grouped_batch": grouped, "large_shape": large}
+
+
 def c4_bench(torch, ff, n_pairs):
     """Config 4: n uneven gray pairs (sides 96..256, translations up to
     +-24 px, 3 levels) as ONE batched call (replayed hipGraph, tuned schedule)
@@ -185,7 +243,10 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time per-pair ff_match_pair calls")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default line-kernel schedule")
+    ap.add_argument("--autotune", action="store_true", help="re-tune the line-kernel schedule first")
+    ap.add_argument("--default-schedule", action="store_true", help="chunks 4, lines 4 everywhere")
+    ap.add_argument("--seednn-only", action="store_true",
+                    help="only time the seed search at the large shape (for counter runs)")
     ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
@@ -202,6 +263,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calib_bytes": n, "copies": 5}), flush=True)
+        return
+    if args.seednn_only:
+        import torch
+        from paper_1805_03517_amd import ff, synth
+        a, b = synth.config1(seed=1)[:2]
+        pair = (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        print(json.dumps(seednn_bench(torch, ff, pair, (1, 1.0, 0))["large_shape"]), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pairs are independent and a "
@@ -222,13 +290,15 @@ def main():
     for _ in range(args.warmup):
         m.match_batch(pairs, outs=outs)
     torch.cuda.synchronize()
-    tuning = None
-    if not args.no_tune:
+    if args.autotune:
         print("[bench] autotuning the line-kernel schedule on this batch", file=sys.stderr, flush=True)
-        tuning = m.autotune(pairs, outs=outs)
-        for _ in range(2):
-            m.match_batch(pairs, outs=outs)
-        torch.cuda.synchronize()
+        m.autotune(pairs, outs=outs)
+    elif not args.default_schedule:
+        m.set_tuning(SCHEDULE_C1)
+    tuning = m.tuning()
+    for _ in range(2):
+        m.match_batch(pairs, outs=outs)
+    torch.cuda.synchronize()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -264,6 +334,10 @@ def main():
     achieved = avg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
     kernels = {k: {"launches": v[0], "avg_us": 1000.0 * v[1] / max(v[0], 1),
                    "share": v[1] / max(sum(x[1] for x in prof.values()), 1e-9)} for k, v in prof.items()}
+
+    print("[bench] seed search MFMA utilisation", file=sys.stderr, flush=True)
+    sl, sms = prof.get("seed_nn", (1, 0.0))
+    seednn = seednn_bench(torch, ff, pairs[0], (sl, sms, args.batch))
 
     plain = None
     if args.plain:
@@ -314,10 +388,13 @@ def main():
                    "global_batch": args.batch, "parallelism": "none (1 GPU)", "schedule": tuning,
                    "consistent_fraction": consistent},
         "roofline": {"bound": "hbm", "kernel": "col_phase", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (TRAFFIC["bytes_per_launch"]
+                                 if TRAFFIC["kernel_sha"] == kernel_sha() and tuning == SCHEDULE_C1 else None),
                      "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": avg_bytes},
         "kernels": kernels,
         "plain": plain,
+        "seed_nn": seednn,
         "serving": serving,
         "batch_c4": batch_c4,
         "cpu_baseline": cpu,

@@ -339,18 +339,40 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 #pragma unroll
         for (int i = 0; i < 4; ++i) best[mq][i] = INT32_MIN;
 
-    const v4i* rec = reinterpret_cast<const v4i*>(P.dbrec[dir ^ 1]);
-    for (int t = t0; t < t1; ++t) {
-        const int n = t * 16 + m;
-        const bool nvalid = n < N;
-        const v4i B = nvalid ? rec[(size_t)n * 4 + g] : v4i{0, 0, 0, 0};
-        const int tl = 2047 - (t - t0);
+    const FF_GLOBAL v4i* rec = (const FF_GLOBAL v4i*)P.dbrec[dir ^ 1];
+    const v4i zero = v4i{0, 0, 0, 0};
+    // full tiles two at a time: key = (score << 11) | (2047 - local tile), one
+    // v_lshl_or per score and one v_max3 per two scores
+    const int tfull = min(t1, N >> 4);
+    int t = t0;
+    for (; t + 1 < tfull; t += 2) {
+        const v4i B0 = rec[(size_t)(t * 16 + m) * 4 + g];
+        const v4i B1 = rec[(size_t)(t * 16 + 16 + m) * 4 + g];
+        const uint32_t tl0 = (uint32_t)(2047 - (t - t0)), tl1 = tl0 - 1u;
 #pragma unroll
         for (int mq = 0; mq < MQ; ++mq) {
-            const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, v4i{0, 0, 0, 0}, 0, 0, 0);
+            const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
+            const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | (uint32_t)tl) : INT32_MIN;
+                const int k0 = (int)(((uint32_t)acc0[i] << 11) | tl0);
+                const int k1 = (int)(((uint32_t)acc1[i] << 11) | tl1);
+                best[mq][i] = max(best[mq][i], max(k0, k1));
+            }
+        }
+    }
+    // at most one remaining tile, possibly the ragged last one of the plane
+    for (; t < t1; ++t) {
+        const int n = t * 16 + m;
+        const bool nvalid = n < N;
+        const v4i B = nvalid ? rec[(size_t)n * 4 + g] : zero;
+        const uint32_t tl = (uint32_t)(2047 - (t - t0));
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq) {
+            const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | tl) : INT32_MIN;
                 best[mq][i] = max(best[mq][i], key);
             }
         }
