@@ -132,16 +132,21 @@ int32_t   ff_serve_inflight(ff_handle h);
 
 /* ---- schedule autotuning -----------------------------------------------
  * The row and column phases run one wave per image line and solve each
- * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves.  Both
- * are scheduling choices only: the sweep's result is the same for every
- * window size, so no choice changes any output.  ff_autotune runs this
- * batch once per candidate (chunks, lines) in {2,4,8} x {2,4,8} (twice, the
- * second timed with events) and keeps, per phase and level, the fastest;
- * it synchronises the stream.  ff_tune_get writes 4 * levels int32
- * (cfg[(phase * levels + level) * 2 + {0: chunks, 1: lines}], phase 0 = row,
- * 1 = column) and returns that count, or -1 if max is too small;
- * ff_tune_set installs such a vector (each entry 2, 4 or 8).  The default
- * is chunks = 4, lines = 4 everywhere.                                    */
+ * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves; with
+ * `staged` = 1 the waves of a block take their windows in lockstep and read
+ * random-search trials from an LDS copy of the windows' target
+ * neighbourhood.  All three are scheduling choices only: the sweep's result
+ * does not depend on the window, and staging changes where a descriptor is
+ * read from, not which one -- no choice changes any output.  Supported
+ * triples: staged 0 with chunks in {1,2,4,8} and lines in {2,4,8}; staged 1 with (chunks,
+ * lines) in {(1,4), (1,8), (1,16), (2,8)}.  ff_autotune runs this batch once
+ * per supported triple (twice, the second timed with events) and keeps, per
+ * phase and level, the fastest; it synchronises the stream.  ff_tune_get
+ * writes 6 * levels int32 (cfg[(phase * levels + level) * 3 + {0: chunks,
+ * 1: lines, 2: staged}], phase 0 = row, 1 = column) and returns that count,
+ * or -1 if max is too small; ff_tune_set installs such a vector
+ * (FF_ERR_INVALID for an unsupported triple).  The default is (4, 4, 0)
+ * everywhere.                                                             */
 ff_status ff_autotune(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
 int32_t   ff_tune_get(ff_handle h, int32_t* cfg, int32_t max);
 ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n);

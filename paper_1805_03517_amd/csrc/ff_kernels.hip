@@ -97,14 +97,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // (2,3) for odd j.  All trial costs are gathered first (independent loads),
 // then selected in trial order with a strict '<', which equals the
 // sequential rule because a trial equal to the running best costs the same.
-template <int RC, bool COL = false>
-__device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a,
-                                              gcu8* __restrict__ DB, int W, int H, int x,
-                                              int y, uint32_t level, uint32_t ctr2,
-                                              const SearchConst& sc)
+// `cost(flow)` evaluates one trial (a global gather, or an LDS read when the
+// caller staged the target neighbourhood).
+template <int RC, typename CostFn>
+__device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, int W, int x, int y, uint32_t level,
+                                              uint32_t ctr2, const SearchConst& sc, CostFn cost)
 {
-    const int R = RC > 0 ? RC : sc.radius;
-    const int J = RC > 0 ? (31 - __builtin_clz((unsigned)(RC > 0 ? RC : 1)) + 1) : sc.trials;
     const int vx = flow_x(bf), vy = flow_y(bf);
     const uint32_t ctr0 = (uint32_t)(y * W + x);
     if constexpr (RC > 0) {
@@ -120,22 +118,21 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, uint4 a
             const int r = RC >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
             cand[j] = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            e[j] = cost_at<COL>(DB, W, H, x, y, cand[j], a);
+            e[j] = cost(cand[j]);
         }
 #pragma unroll
         for (int j = 0; j < JC; ++j)
             if (e[j] < bc) { bc = e[j]; bf = cand[j]; }
-        (void)R; (void)J;
     } else {
         uint4 u = make_uint4(0, 0, 0, 0);
-        for (int j = 0; j < J; ++j) {
+        for (int j = 0; j < sc.trials; ++j) {
             if ((j & 1) == 0) u = philox4x32_10(make_uint4(ctr0, level, ctr2, (uint32_t)(j >> 1)), sc.key0, sc.key1);
             const uint32_t ux = (j & 1) ? u.z : u.x;
             const uint32_t uy = (j & 1) ? u.w : u.y;
-            const int r = R >> j;
+            const int r = sc.radius >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
             const uint32_t c = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            const int32_t ej = cost_at<COL>(DB, W, H, x, y, c, a);
+            const int32_t ej = cost(c);
             if (ej < bc) { bc = ej; bf = c; }
         }
     }
@@ -460,11 +457,193 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // random search needs only its own swept state, so it runs on the window
 // right after convergence, before the write.  Both passes use the same
 // window partition, so every lane re-reads exactly what it wrote.
+//
+// STG (staged random search): the WPB waves of a block take the windows of
+// their WPB adjacent lines in lockstep.  After the sweep of a window every
+// wave publishes the flow of one sample pixel; the block takes the median
+// of those flows as the window's displacement and loads B's descriptors of
+// a fixed RI x RJ neighbourhood -- the window's lines and positions moved
+// by that displacement, widened on both sides -- into LDS with coalesced
+// loads.  Trials that land inside it read LDS; trials outside it (large
+// radii, pixels whose flow departs from the median) load from global
+// memory as before.  The trials, their order and their costs are unchanged.
+//
 // upto (for intermediate captures): row 1 = LR, 2 = +RL, 3 = +RS0;
 // col 4 = TB, 5 = +RS1, 6 = +BT, 7 = +RS2.
-// WPB lines (waves) per block; grid (ceil(lines / WPB), 2 * pairs).  CH and
-// WPB only change scheduling, never the result.
-template <int RC, bool COL, int CH, int WPB>
+// WPB lines (waves) per block; grid (ceil(lines / WPB), 2 * pairs).  CH, WPB
+// and STG only change scheduling and data movement, never the result.
+// One sweep pass of one line, software-pipelined across windows (plain
+// path, compile-time radius).  Window w+1's state and own descriptors are
+// loaded while window w relaxes; window w's random-search trials are
+// gathered at its end and selected during window w+1's first relaxation
+// round, so their memory latency overlaps other work.  The trials, their
+// order and the selection rule are those of random_search().
+template <int RC, bool COL, int CH>
+__device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
+                                                    gi2* __restrict__ S, int W, int H, int len, int line,
+                                                    int lane, bool fwd, bool rs, uint32_t level, uint32_t ctr2,
+                                                    const SearchConst& sc)
+{
+    constexpr int WIN = 64 * CH;
+    constexpr int JC = 31 - __builtin_clz((unsigned)RC) + 1;
+    const int nwin = (len + WIN - 1) / WIN;
+    auto wstart = [&](int wi) { return (fwd ? wi : nwin - 1 - wi) * WIN; };
+
+    uint32_t f0[CH], nf0[CH];
+    int32_t c0[CH], nc0[CH];
+    uint4 a[CH], na[CH];
+    auto load_window = [&](int w0, uint32_t* F, int32_t* C, uint4* A) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int p = w0 + 64 * c + lane;
+            const bool valid = p < len;
+            const i32x2 st = valid ? S[p] : i32x2{0, kInf};
+            A[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
+            F[c] = (uint32_t)st.x;
+            C[c] = st.y;
+        }
+    };
+    load_window(wstart(0), f0, c0, a);
+
+    // random search of the previous window, gathered but not yet selected
+    bool pend = false;
+    int pw0 = 0;
+    uint32_t pbf[CH], pcand[CH][JC];
+    int32_t pbc[CH];
+    uint4 pdesc[CH][JC], pa[CH];
+    uint32_t pin[CH];                                            // bit j: trial j lands inside image B
+    auto finish = [&]() {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int p = pw0 + 64 * c + lane;
+            if (p >= len) continue;
+            uint32_t bf = pbf[c];
+            int32_t bc = pbc[c];
+#pragma unroll
+            for (int j = 0; j < JC; ++j) {
+                const int32_t e = ((pin[c] >> j) & 1u) ? sad16(pa[c], pdesc[c][j]) : kInf;
+                if (e < bc) { bc = e; bf = pcand[c][j]; }
+            }
+            S[p] = i32x2{(int)bf, bc};
+        }
+    };
+
+    uint32_t carry = 0;
+    for (int wi = 0; wi < nwin; ++wi) {
+        const int w0 = wstart(wi);
+        if (wi + 1 < nwin) load_window(wstart(wi + 1), nf0, nc0, na);
+        uint32_t lp[CH], h[CH];
+        int32_t le[CH];
+        bool hp[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int p = w0 + 64 * c + lane;
+            hp[c] = p < len && (fwd ? p > 0 : p + 1 < len);
+            lp[c] = f0[c];
+            le[c] = c0[c];
+            h[c] = f0[c];
+        }
+        while (true) {
+            uint32_t pred[CH];
+            bool need[CH];
+            bool anyn = false;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                if (fwd) {
+                    const uint32_t up = (uint32_t)__shfl_up((int)h[c], 1, 64);
+                    const uint32_t edge = c == 0 ? carry : (uint32_t)__builtin_amdgcn_readlane((int)h[c > 0 ? c - 1 : 0], 63);
+                    pred[c] = lane == 0 ? edge : up;
+                } else {
+                    const uint32_t dn = (uint32_t)__shfl_down((int)h[c], 1, 64);
+                    const uint32_t edge = c == CH - 1 ? carry
+                                                      : (uint32_t)__builtin_amdgcn_readlane((int)h[c < CH - 1 ? c + 1 : c], 0);
+                    pred[c] = lane == 63 ? edge : dn;
+                }
+                need[c] = hp[c] && pred[c] != lp[c];
+                anyn |= need[c];
+            }
+            const bool go = __any(anyn);
+            if (go) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (need[c]) {
+                        const int p = w0 + 64 * c + lane;
+                        lp[c] = pred[c];
+                        le[c] = pred[c] == f0[c] ? c0[c]
+                                                 : cost_at<COL>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
+                    }
+                }
+            }
+            if (pend) {
+                finish();
+                pend = false;
+            }
+            if (!go) break;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) h[c] = le[c] < c0[c] ? lp[c] : f0[c];
+        }
+        carry = fwd ? (uint32_t)__builtin_amdgcn_readlane((int)h[CH - 1], 63)
+                    : (uint32_t)__builtin_amdgcn_readlane((int)h[0], 0);
+        if (rs) {
+            // issue this window's trials (Philox offsets, gathers); select later
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int p = w0 + 64 * c + lane;
+                pbf[c] = h[c];
+                pbc[c] = le[c] < c0[c] ? le[c] : c0[c];
+                pa[c] = a[c];
+                pin[c] = 0;
+                if (p >= len) continue;
+                const int x = COL ? line : p, y = COL ? p : line;
+                const int vx = flow_x(h[c]), vy = flow_y(h[c]);
+                const uint32_t ctr0 = (uint32_t)(y * W + x);
+                uint4 u = make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < JC; ++j) {
+                    if ((j & 1) == 0) u = philox4x32_10(make_uint4(ctr0, level, ctr2, (uint32_t)(j >> 1)), sc.key0, sc.key1);
+                    const uint32_t ux = (j & 1) ? u.z : u.x;
+                    const uint32_t uy = (j & 1) ? u.w : u.y;
+                    const int r = RC >> j;
+                    const uint32_t span = 2u * (uint32_t)r + 1u;
+                    const int qdx = (int)(ux % span) - r, qdy = (int)(uy % span) - r;
+                    pcand[c][j] = pack_flow(vx + qdx, vy + qdy);
+                    const int qx = x + flow_x(pcand[c][j]), qy = y + flow_y(pcand[c][j]);
+                    const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H;
+                    pin[c] |= in ? (1u << j) : 0u;
+                    pdesc[c][j] = in ? ld16(DB + pix<COL>(qx, qy, W, H) * 16) : make_uint4(0, 0, 0, 0);
+                }
+            }
+            pend = true;
+            pw0 = w0;
+        } else {
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int p = w0 + 64 * c + lane;
+                if (p < len) S[p] = i32x2{(int)h[c], le[c] < c0[c] ? le[c] : c0[c]};
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            f0[c] = nf0[c];
+            c0[c] = nc0[c];
+            a[c] = na[c];
+        }
+    }
+    if (pend) finish();
+}
+
+// Staged neighbourhood: RJ lines (the block's WPB lines widened by 12 on
+// each side, 8 for 16-line blocks) by RI positions (the window widened to
+// fill 51 KiB of LDS for 64-px windows -- three blocks per CU -- or 72 KiB
+// for 128-px windows).
+template <int CH, int WPB>
+struct StageDims {
+    static constexpr int RJ = WPB + (WPB >= 16 ? 16 : 24);
+    static constexpr int RI = (CH == 1 ? 3264 : 4608) / RJ;
+    static constexpr int CAP = RI * RJ;
+};
+
+template <int RC, bool COL, int CH, int WPB, bool STG>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
                                                          int iter, int upto, SearchConst sc)
 {
@@ -475,14 +654,24 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const LevelDev& L = P.lv[level];
     const int W = L.W, H = L.H;
     const int len = COL ? H : W, nlines = COL ? W : H;
-    const int lane = threadIdx.x & 63;
-    const int line = bx * WPB + (threadIdx.x >> 6);
-    if (line >= nlines) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int line0 = bx * WPB;
+    const int line = line0 + wave;
+    if (line0 >= nlines) return;                                 // whole block idle: uniform
+    const bool active = line < nlines;
+    if (!STG && !active) return;
     gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
     gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
     constexpr int WIN = 64 * CH;
     const int nwin = (len + WIN - 1) / WIN;
+
+    using SD = StageDims<CH, WPB>;
+    constexpr int RI = SD::RI, RJ = SD::RJ;
+    __shared__ uint4 region[STG ? SD::CAP : 1];
+    __shared__ int sample[2][WPB][2];                            // per parity: a flow sample (i, j) per line
+    __shared__ int sample_ok[2][WPB];
+    int gw = 0;                                                  // windows staged so far (slot parity)
 
     for (int pass = 0; pass < 2; ++pass) {
         const bool fwd = pass == 0;
@@ -498,6 +687,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             rs_pass = fwd ? 1 : 2;
         }
         const uint32_t ctr2 = ((uint32_t)iter << 2) | rs_pass;
+        if constexpr (!STG && RC > 0 && CH <= 2) {
+            line_pass_pipelined<RC, COL, CH>(DA, DB, S, W, H, len, line, lane, fwd, rs, (uint32_t)level, ctr2, sc);
+            continue;
+        }
         uint32_t carry = 0;
         for (int wi = 0; wi < nwin; ++wi) {
             const int w0 = (fwd ? wi : nwin - 1 - wi) * WIN;
@@ -508,7 +701,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
-                const bool valid = p < len;
+                const bool valid = active && p < len;
                 const i32x2 st = valid ? S[p] : i32x2{0, kInf};
                 a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
                 f0[c] = (uint32_t)st.x;
@@ -518,7 +711,56 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                 le[c] = c0[c];
                 h[c] = f0[c];
             }
-            while (true) {
+            // ---- staging of the window's random-search neighbourhood, issued
+            // before the sweep so the copy overlaps the relaxation rounds
+            int si0 = 0, sj0 = 0;
+            if (STG && rs) {
+                const int slot = gw & 1;
+                if (lane == 32) {                                // sample: lane 32 of the first chunk
+                    sample[slot][wave][0] = COL ? flow_y(f0[0]) : flow_x(f0[0]);
+                    sample[slot][wave][1] = COL ? flow_x(f0[0]) : flow_y(f0[0]);
+                    sample_ok[slot][wave] = (active && w0 + 32 < len) ? 1 : 0;
+                }
+                __syncthreads();
+                // lower median of the published samples, per component: lane k < WPB
+                // holds sample k and counts the samples ordered before it (ties by
+                // index), so exactly one lane holds each rank
+                const bool okk = lane < WPB && sample_ok[slot][lane < WPB ? lane : 0];
+                const int vi = okk ? sample[slot][lane][0] : 0, vj = okk ? sample[slot][lane][1] : 0;
+                const unsigned long long okmask = __ballot(okk);
+                const int nv = __popcll(okmask);
+                int rank_i = 0, rank_j = 0;
+#pragma unroll
+                for (int k = 0; k < WPB; ++k) {
+                    if (!((okmask >> k) & 1ull)) continue;
+                    const int ik = __builtin_amdgcn_readlane(vi, k), jk = __builtin_amdgcn_readlane(vj, k);
+                    rank_i += (ik < vi || (ik == vi && k < lane)) ? 1 : 0;
+                    rank_j += (jk < vj || (jk == vj && k < lane)) ? 1 : 0;
+                }
+                const int mid = (nv - 1) >> 1;
+                const unsigned long long hi = __ballot(okk && rank_i == mid), hj = __ballot(okk && rank_j == mid);
+                const int mi = nv ? __builtin_amdgcn_readlane(vi, __ffsll((long long)hi) - 1) : 0;
+                const int mj = nv ? __builtin_amdgcn_readlane(vj, __ffsll((long long)hj) - 1) : 0;
+                si0 = w0 + mi - (RI - WIN) / 2;
+                sj0 = line0 + mj - (RJ - WPB) / 2;
+                // direct global -> LDS copies (global_load_lds_dwordx4): lane l of a
+                // row chunk lands at LDS base + 16 l, lanes outside the image or the
+                // row stay masked off
+                for (int rj = wave; rj < RJ; rj += WPB) {
+                    const int gj = sj0 + rj;
+                    if (gj < 0 || gj >= nlines) continue;
+#pragma unroll
+                    for (int k = 0; k < (RI + 63) / 64; ++k) {
+                        const int ri = 64 * k + lane, gi = si0 + ri;
+                        if (ri < RI && gi >= 0 && gi < len)
+                            __builtin_amdgcn_global_load_lds(
+                                (const FF_GLOBAL void*)(DB + ((size_t)gj * len + gi) * 16),
+                                (__attribute__((address_space(3))) void*)&region[rj * RI + 64 * k], 16, 0, 0);
+                    }
+                }
+                ++gw;
+            }
+            while (active) {
                 uint32_t pred[CH];
                 bool need[CH];
                 bool anyn = false;
@@ -552,15 +794,35 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             }
             carry = fwd ? (uint32_t)__builtin_amdgcn_readlane((int)h[CH - 1], 63)
                         : (uint32_t)__builtin_amdgcn_readlane((int)h[0], 0);
+
+            if (STG && rs) {
+                __builtin_amdgcn_s_waitcnt(0);                   // staged descriptors have landed in LDS
+                __syncthreads();
+            }
+
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
-                if (p >= len) continue;
+                if (!(active && p < len)) continue;
                 uint32_t bf = h[c];
                 int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
-                if (rs)
-                    random_search<RC, COL>(bf, bc, a[c], DB, W, H, COL ? line : p, COL ? p : line, (uint32_t)level,
-                                           ctr2, sc);
+                const int x = COL ? line : p, y = COL ? p : line;
+                if (rs) {
+                    const uint4 ac = a[c];
+                    if (STG) {
+                        random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc, [&](uint32_t f) -> int32_t {
+                            const int qx = x + flow_x(f), qy = y + flow_y(f);
+                            if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
+                            const int ri = (COL ? qy : qx) - si0, rj = (COL ? qx : qy) - sj0;
+                            if ((unsigned)ri < (unsigned)RI && (unsigned)rj < (unsigned)RJ)
+                                return sad16(ac, region[rj * RI + ri]);
+                            return sad16(ac, ld16(DB + pix<COL>(qx, qy, W, H) * 16));
+                        });
+                    } else {
+                        random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc,
+                                          [&](uint32_t f) { return cost_at<COL>(DB, W, H, x, y, f, ac); });
+                    }
+                }
                 S[p] = i32x2{(int)bf, bc};
             }
         }
@@ -676,41 +938,45 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
 {
     hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
 }
-template <int RC, bool COL, int CH, int WPB>
+template <int RC, bool COL, int CH, int WPB, bool STG>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
                    hipStream_t st)
 {
-    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
+    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
                        dim3(64 * WPB), 0, st, d, level, iter, upto, sc);
 }
 
 template <int RC, bool COL>
-bool launch_line_rc(int ch, int wpb, const PairDev* d, int npairs, int level, int iter, int upto,
+bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
                     const SearchConst& sc, int nlines, hipStream_t st)
 {
-#define FF_LINE_CASE(C, B)                                                                    \
-    if (ch == C && wpb == B) {                                                                \
-        launch_line_t<RC, COL, C, B>(d, npairs, level, iter, upto, sc, nlines, st);          \
+#define FF_LINE_CASE(C, B, G)                                                                 \
+    if (ch == C && wpb == B && stg == G) {                                                    \
+        launch_line_t<RC, COL, C, B, G != 0>(d, npairs, level, iter, upto, sc, nlines, st);  \
         return true;                                                                          \
     }
-    FF_LINE_CASE(2, 2) FF_LINE_CASE(2, 4) FF_LINE_CASE(2, 8)
-    FF_LINE_CASE(4, 2) FF_LINE_CASE(4, 4) FF_LINE_CASE(4, 8)
-    FF_LINE_CASE(8, 2) FF_LINE_CASE(8, 4) FF_LINE_CASE(8, 8)
+    FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
+    FF_LINE_CASE(2, 2, 0) FF_LINE_CASE(2, 4, 0) FF_LINE_CASE(2, 8, 0)
+    FF_LINE_CASE(4, 2, 0) FF_LINE_CASE(4, 4, 0) FF_LINE_CASE(4, 8, 0)
+    FF_LINE_CASE(8, 2, 0) FF_LINE_CASE(8, 4, 0) FF_LINE_CASE(8, 8, 0)
+    FF_LINE_CASE(1, 4, 1) FF_LINE_CASE(1, 8, 1) FF_LINE_CASE(1, 16, 1) FF_LINE_CASE(2, 8, 1)
 #undef FF_LINE_CASE
     return false;
 }
 
 // One row or column phase of every pair and direction at one level.  ch =
-// chunks of 64 px per relaxation window, wpb = lines per block; both in
-// {2, 4, 8}.  Returns false for an unsupported (ch, wpb).
-bool launch_line_phase(bool col, int ch, int wpb, const PairDev* d, int npairs, int level, int iter, int upto,
-                       const SearchConst& sc, int nlines, hipStream_t st)
+// chunks of 64 px per relaxation window, wpb = lines per block, stg = staged
+// random search; supported: stg 0 with ch in {1, 2, 4, 8} and wpb in {2, 4, 8}
+// (ch <= 2 runs the software-pipelined pass at radius 16); stg 1 with
+// (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false otherwise.
+bool launch_line_phase(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
+                       int upto, const SearchConst& sc, int nlines, hipStream_t st)
 {
     if (sc.radius == 16)
-        return col ? launch_line_rc<16, true>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st)
-                   : launch_line_rc<16, false>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st);
-    return col ? launch_line_rc<0, true>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st)
-               : launch_line_rc<0, false>(ch, wpb, d, npairs, level, iter, upto, sc, nlines, st);
+        return col ? launch_line_rc<16, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st)
+                   : launch_line_rc<16, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st);
+    return col ? launch_line_rc<0, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st)
+               : launch_line_rc<0, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st);
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

@@ -30,7 +30,7 @@ void launch_desc(const PairDev*, int, int, int, int, hipStream_t);
 void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, hipStream_t);
-bool launch_line_phase(bool, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
+bool launch_line_phase(bool, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
@@ -77,9 +77,11 @@ struct ff_ctx {
     std::vector<ProfRec> prof;
     struct ServeState* serve = nullptr;         // serving engine, created on first use
     // line-kernel schedule per phase (0 row, 1 col) and level: chunks of 64 px
-    // per relaxation window and lines per block (set by ff_autotune / ff_tune_set)
+    // per relaxation window, lines per block and LDS staging of the random
+    // search (set by ff_autotune / ff_tune_set)
     int tune_ch[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
     int tune_wpb[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
+    int tune_stg[2][kMaxLevels] = {};          // 1 = random search reads a staged LDS neighbourhood
 };
 
 // Serving: continuous batching over `lanes` concurrent cohorts.  Each lane
@@ -404,11 +406,11 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         for (int t = 0; t < p.iters; ++t) {
             const bool last = stop_here && stop.st.iter == t;
             const int upto = last ? stop.st.step : 7;
-            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], d, n, l, t,
+            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], d, n, l, t,
                                                 std::min(upto, 3), sc, D.maxH[l], st));
             if (upto >= 4) {
                 FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 1, D.maxW[l], D.maxH[l], st));
-                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], d, n, l, t, upto, sc,
+                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], d, n, l, t, upto, sc,
                                                     D.maxW[l], st));
                 FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
             }
@@ -568,15 +570,18 @@ void drop_graphs(ff_ctx* h)
 // candidate, so tuning never changes an output.
 ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
 {
-    static const int kCand[][2] = {{2, 2}, {2, 4}, {2, 8}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {8, 8}};
+    static const int kCand[][3] = {{1, 2, 0}, {1, 4, 0}, {1, 8, 0}, {2, 2, 0}, {2, 4, 0}, {2, 8, 0},
+                                   {4, 2, 0}, {4, 4, 0}, {4, 8, 0}, {8, 2, 0}, {8, 4, 0}, {8, 8, 0},
+                                   {1, 4, 1}, {1, 8, 1}, {1, 16, 1}, {2, 8, 1}};
     const int L = h->prm.levels;
     double best[2][kMaxLevels];
-    int bch[2][kMaxLevels], bwpb[2][kMaxLevels];
+    int bc[2][kMaxLevels][3];
     for (int ph = 0; ph < 2; ++ph)
         for (int l = 0; l < L; ++l) {
             best[ph][l] = 1e30;
-            bch[ph][l] = h->tune_ch[ph][l];
-            bwpb[ph][l] = h->tune_wpb[ph][l];
+            bc[ph][l][0] = h->tune_ch[ph][l];
+            bc[ph][l][1] = h->tune_wpb[ph][l];
+            bc[ph][l][2] = h->tune_stg[ph][l];
         }
     const bool was_on = h->prof_on;
     std::vector<Timed> discard;
@@ -587,6 +592,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
             for (int l = 0; l < L; ++l) {
                 h->tune_ch[ph][l] = c[0];
                 h->tune_wpb[ph][l] = c[1];
+                h->tune_stg[ph][l] = c[2];
             }
         for (int rep = 0; rep < 2; ++rep) {
             h->prof_on = rep == 1;
@@ -612,14 +618,14 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
             for (int l = 0; l < L; ++l)
                 if (t[ph][l] < best[ph][l]) {
                     best[ph][l] = t[ph][l];
-                    bch[ph][l] = c[0];
-                    bwpb[ph][l] = c[1];
+                    for (int k = 0; k < 3; ++k) bc[ph][l][k] = c[k];
                 }
     }
     for (int ph = 0; ph < 2; ++ph)
         for (int l = 0; l < L; ++l) {
-            h->tune_ch[ph][l] = bch[ph][l];
-            h->tune_wpb[ph][l] = bwpb[ph][l];
+            h->tune_ch[ph][l] = bc[ph][l][0];
+            h->tune_wpb[ph][l] = bc[ph][l][1];
+            h->tune_stg[ph][l] = bc[ph][l][2];
         }
     h->prof_on = was_on;
     drop_graphs(h);
@@ -871,27 +877,32 @@ ff_status ff_autotune(ff_handle h, const ff_pair* pairs, int32_t n, void* stream
 int32_t ff_tune_get(ff_handle h, int32_t* cfg, int32_t max)
 {
     const int L = h ? h->prm.levels : 0;
-    if (!h || max < 4 * L || !cfg) return -1;
+    if (!h || max < 6 * L || !cfg) return -1;
     for (int ph = 0; ph < 2; ++ph)
         for (int l = 0; l < L; ++l) {
-            cfg[(ph * L + l) * 2 + 0] = h->tune_ch[ph][l];
-            cfg[(ph * L + l) * 2 + 1] = h->tune_wpb[ph][l];
+            cfg[(ph * L + l) * 3 + 0] = h->tune_ch[ph][l];
+            cfg[(ph * L + l) * 3 + 1] = h->tune_wpb[ph][l];
+            cfg[(ph * L + l) * 3 + 2] = h->tune_stg[ph][l];
         }
-    return 4 * L;
+    return 6 * L;
 }
 
 ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n)
 {
     if (!h) return FF_ERR_INVALID;
     const int L = h->prm.levels;
-    if (!cfg || n != 4 * L) return fail(h, FF_ERR_INVALID, "tuning vector must hold 4 * levels entries");
-    for (int i = 0; i < n; ++i)
-        if (cfg[i] != 2 && cfg[i] != 4 && cfg[i] != 8)
-            return fail(h, FF_ERR_INVALID, "chunks per window and lines per block must be 2, 4 or 8");
+    if (!cfg || n != 6 * L) return fail(h, FF_ERR_INVALID, "tuning vector must hold 6 * levels entries");
+    for (int i = 0; i < n; i += 3) {
+        const int ch = cfg[i], wpb = cfg[i + 1], stg = cfg[i + 2];
+        const bool plain = stg == 0 && (ch == 1 || ch == 2 || ch == 4 || ch == 8) && (wpb == 2 || wpb == 4 || wpb == 8);
+        const bool staged = stg == 1 && ((ch == 1 && (wpb == 4 || wpb == 8 || wpb == 16)) || (ch == 2 && wpb == 8));
+        if (!plain && !staged) return fail(h, FF_ERR_INVALID, "unsupported (chunks, lines, staged) triple");
+    }
     for (int ph = 0; ph < 2; ++ph)
         for (int l = 0; l < L; ++l) {
-            h->tune_ch[ph][l] = cfg[(ph * L + l) * 2 + 0];
-            h->tune_wpb[ph][l] = cfg[(ph * L + l) * 2 + 1];
+            h->tune_ch[ph][l] = cfg[(ph * L + l) * 3 + 0];
+            h->tune_wpb[ph][l] = cfg[(ph * L + l) * 3 + 1];
+            h->tune_stg[ph][l] = cfg[(ph * L + l) * 3 + 2];
         }
     drop_graphs(h);
     return FF_OK;

@@ -253,7 +253,7 @@ class Matcher:
         return self.tuning()
 
     def tuning(self):
-        n = 4 * self.params.levels
+        n = 6 * self.params.levels
         buf = (ctypes.c_int32 * n)()
         if lib().ff_tune_get(self._h, buf, n) != n:
             self._check(FF_ERR_INVALID)

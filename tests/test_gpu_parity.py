@@ -52,10 +52,12 @@ def _compare_outputs(ref, got, tag):
             raise AssertionError(f"{tag}: {k} differs at {len(bad)} places, first {bad[:3].tolist()}")
 
 
-def _run_pair(torch, ffm, orc, i1, i2, p, tag):
+def _run_pair(torch, ffm, orc, i1, i2, p, tag, schedule=None):
     say(tag, "shape", i1.shape, "levels", p.levels, "stride", p.seed_stride, "R", p.rs_radius,
-        "eps", p.fb_eps, "entry ff_match_pair")
+        "eps", p.fb_eps, "entry ff_match_pair", "schedule", schedule)
     m = _matcher(ffm, p)
+    if schedule is not None:
+        m.set_tuning(schedule)
     got = m.match(_dev(torch, i1), _dev(torch, i2))
     torch.cuda.synchronize()
     ref = orc.match(i1, i2, p)
@@ -125,6 +127,19 @@ def test_config2_end_to_end(torch, ffm, orc):
     _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=4), "config2 1024x436 rgb")
 
 
+@pytest.mark.parametrize("cfg", ["config1", "config2"])
+def test_staged_schedule_end_to_end(torch, ffm, orc, cfg):
+    i1, i2, _ = getattr(synth, cfg)()
+    _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=4), f"{cfg} staged", schedule=_staged_schedule(4))
+
+
+@pytest.mark.parametrize("cfg", ["config1", "config2"])
+def test_pipelined_schedule_end_to_end(torch, ffm, orc, cfg):
+    i1, i2, _ = getattr(synth, cfg)()
+    _run_pair(torch, ffm, orc, i1, i2, _prm(orc, levels=4), f"{cfg} pipelined",
+              schedule=[1, 4, 0] * 4 + [2, 8, 0] * 4)
+
+
 EDGE_CASES = [
     # (W, H, C, levels, stride, radius, eps, iters)
     (64, 48, 1, 3, 3, 16, 1, 2),
@@ -141,9 +156,17 @@ EDGE_CASES = [
 ]
 
 
+STAGED = {"row": (1, 8, 1), "col": (2, 8, 1)}
+
+
+def _staged_schedule(levels):
+    return list(STAGED["row"]) * levels + list(STAGED["col"]) * levels
+
+
+@pytest.mark.parametrize("staged", [False, True, "pipelined"], ids=["direct", "staged", "pipelined"])
 @pytest.mark.parametrize("case", EDGE_CASES, ids=[f"{c[0]}x{c[1]}c{c[2]}L{c[3]}s{c[4]}R{c[5]}e{c[6]}T{c[7]}"
                                                   for c in EDGE_CASES])
-def test_edge_shapes(torch, ffm, orc, case):
+def test_edge_shapes(torch, ffm, orc, case, staged):
     W, H, C, L, st, R, eps, T = case
     rng = np.random.default_rng(W * 7919 + H)
     d = (int(rng.integers(-6, 7)), int(rng.integers(-6, 7)))
@@ -154,7 +177,12 @@ def test_edge_shapes(torch, ffm, orc, case):
         i1 = np.stack([c[0] for c in chans], -1)
         i2 = np.stack([c[1] for c in chans], -1)
     p = _prm(orc, levels=L, seed_stride=st, iters=T, rs_radius=R, fb_eps=eps)
-    _run_pair(torch, ffm, orc, i1, i2, p, f"edge {case}")
+    sched = None
+    if staged == "pipelined":
+        sched = [1, 8, 0] * L + [2, 4, 0] * L
+    elif staged:
+        sched = _staged_schedule(L)
+    _run_pair(torch, ffm, orc, i1, i2, p, f"edge {case} schedule={staged}", schedule=sched)
 
 
 def test_periodic_texture_seed_ties(torch, ffm, orc):
@@ -330,8 +358,10 @@ def test_schedule_tuning_never_changes_output(torch, ffm, orc):
     _compare_outputs(r0, ref[1], "default schedule vs oracle")
     say("autotune")
     cfg = m.autotune(dev)
-    assert len(cfg) == 16 and all(v in (2, 4, 8) for v in cfg)
-    for trial in [cfg, [2] * 16, [8] * 16, [2, 8] * 8, [8, 2] * 8]:
+    assert len(cfg) == 24 and all(cfg[i + 2] in (0, 1) for i in range(0, 24, 3))
+    trials = [cfg, [2, 2, 0] * 8, [8, 8, 0] * 8, [2, 8, 0, 8, 2, 0] * 4, [1, 8, 1] * 8, [1, 16, 1] * 8,
+              [1, 4, 1] * 8, [2, 8, 1] * 8, [1, 8, 1, 4, 4, 0] * 4, [1, 2, 0] * 8, [1, 8, 0, 2, 4, 0] * 4]
+    for trial in trials:
         say("schedule", trial)
         m.set_tuning(trial)
         got = m.match_batch(dev)
@@ -340,7 +370,9 @@ def test_schedule_tuning_never_changes_output(torch, ffm, orc):
             for key in o1:
                 assert torch.equal(o1[key], o2[key]), (trial, key)
     with pytest.raises(ffm.FFError):
-        m.set_tuning([3] * 16)
+        m.set_tuning([3, 3, 0] * 8)
+    with pytest.raises(ffm.FFError):
+        m.set_tuning([4, 4, 1] * 8)          # staging is not built for 256-px windows
     m.close()
 
 
