@@ -57,6 +57,8 @@ def lib():
         l.ffo_down2.argtypes = [P, i, i, P]
         l.ffo_descriptors.argtypes = [P, i, i, P]
         l.ffo_seed_nn.argtypes = [P, P, i, i, i, P]
+        l.ffo_nearest.argtypes = [P, P, i]
+        l.ffo_nearest.restype = ctypes.c_int32
         l.ffo_philox4x32_10.argtypes = [P, P, P]
         l.ffo_cost.argtypes = [P, P, i, i, i, i, i, i]
         l.ffo_cost.restype = ctypes.c_int32
@@ -117,6 +119,14 @@ def seed_nn(DA: np.ndarray, DB: np.ndarray, stride: int) -> np.ndarray:
     out = np.empty((nsy, nsx), np.int32)
     lib().ffo_seed_nn(_p(DA), _p(DB), W, H, stride, _p(out))
     return out
+
+
+def nearest(a: np.ndarray, DB: np.ndarray) -> int:
+    """Sec. 3.1 seed search for one query descriptor: lowest index of the
+    minimum squared L2 distance over all descriptors of DB."""
+    a = np.ascontiguousarray(a, dtype=np.int8).reshape(16)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    return int(lib().ffo_nearest(_p(a), _p(DB), DB.size // 16))
 
 
 def philox(ctr, key) -> np.ndarray:

@@ -143,6 +143,21 @@ void ffo_seed_nn(const int8_t* DA, const int8_t* DB, int W, int H, int stride, i
         }
 }
 
+int32_t ffo_nearest(const int8_t* a, const int8_t* DB, int N)
+{
+    int32_t best = INT32_MAX, arg = -1;
+    for (int q = 0; q < N; ++q) {
+        const int8_t* b = DB + (size_t)q * FFO_K;
+        int32_t d = 0;
+        for (int k = 0; k < FFO_K; ++k) {
+            int t = (int)a[k] - (int)b[k];
+            d += t * t;
+        }
+        if (d < best) { best = d; arg = q; }
+    }
+    return arg;
+}
+
 /* -------------------------------------------------------------- Philox -- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11): ten rounds of a 4-word S-P network.  A round

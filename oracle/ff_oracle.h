@@ -48,6 +48,10 @@ void ffo_descriptors(const uint8_t* P, int W, int H, int8_t* D);
  * of B, squared L2 over the descriptors, ties to the lowest linear index.
  * idx has ceil(H/stride) * ceil(W/stride) entries, seed-row-major.       */
 void ffo_seed_nn(const int8_t* DA, const int8_t* DB, int W, int H, int stride, int32_t* idx);
+/* The same search for one query descriptor a against the N descriptors of
+ * DB: index of the first minimum of the squared L2 distance.  Lets a test
+ * check single seeds of a plane too large to search whole.               */
+int32_t ffo_nearest(const int8_t* a, const int8_t* DB, int N);
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11).                        */
 void ffo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Matching cost: SAD of the two descriptors, INF when p+f leaves image B.  */

@@ -292,12 +292,17 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
 
 // Exact nearest neighbour of every seed of A among all coarsest pixels of B
 // (Sec. 3.1 initial matches; the exact answer the kd-tree approximates).
-// A wave holds 16*MQ seeds as MFMA A operands and streams one split of the
-// database; per lane and seed row it keeps max((score << 11) | (2047 - t)),
-// so equal scores prefer the lower tile, then reduces over the 16 columns
-// preferring the lower column, and merges splits with a 64-bit atomicMax on
+// A block of 4 waves holds 4 x 16*MQ seeds as MFMA A operands and streams
+// one split of the database: chunks of kSeedChunk tiles are copied once per
+// block into LDS (direct global -> LDS loads) and read by all four waves, so
+// the database crosses L2 once per block instead of once per wave.  Per lane
+// and seed row a wave keeps max((score << 11) | (2047 - t)), so equal scores
+// prefer the lower tile, then reduces over the 16 columns preferring the
+// lower column, and merges splits with a 64-bit atomicMax on
 // (score + 2^20) << 32 | ~index -- the lowest index wins every tie.
 // grid (ceil(seed tiles / 4), splits, 2 * pairs), 256 threads.
+constexpr int kSeedChunk = 16;                                   // tiles (16 KiB) per LDS chunk
+
 template <int MQ>
 __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pairs, int level,
                                                 int stride, int tiles_per_split)
@@ -307,13 +312,14 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     const LevelDev& L = P.lv[level];
     const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int qbase = (blockIdx.x * 4 + wave) * 16 * MQ;
-    if (qbase >= Q) return;
+    if (blockIdx.x * 4 * 16 * MQ >= Q) return;                   // no seeds in this block: uniform
     const int ntiles = (N + 15) >> 4;
     const int t0 = blockIdx.y * tiles_per_split;
-    if (t0 >= ntiles) return;
+    if (t0 >= ntiles) return;                                    // uniform
     const int t1 = min(t0 + tiles_per_split, ntiles);
+    const int qbase = (blockIdx.x * 4 + wave) * 16 * MQ;         // may exceed Q: the wave still loads
     const int m = lane & 15, g = lane >> 4;
+    __shared__ v4i tiles[kSeedChunk * 64];
 
     v4i A[MQ];
 #pragma unroll
@@ -338,42 +344,59 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 
     const FF_GLOBAL v4i* rec = (const FF_GLOBAL v4i*)P.dbrec[dir ^ 1];
     const v4i zero = v4i{0, 0, 0, 0};
-    // full tiles two at a time: key = (score << 11) | (2047 - local tile), one
-    // v_lshl_or per score and one v_max3 per two scores
-    const int tfull = min(t1, N >> 4);
-    int t = t0;
-    for (; t + 1 < tfull; t += 2) {
-        const v4i B0 = rec[(size_t)(t * 16 + m) * 4 + g];
-        const v4i B1 = rec[(size_t)(t * 16 + 16 + m) * 4 + g];
-        const uint32_t tl0 = (uint32_t)(2047 - (t - t0)), tl1 = tl0 - 1u;
+    const uint32_t nrec4 = (uint32_t)N * 4u;                     // valid 16-byte groups of the database
+    const uint32_t lane_off = (uint32_t)(m * 4 + g);
+    for (int tb = t0; tb < t1; tb += kSeedChunk) {
+        const int nt = min(kSeedChunk, t1 - tb);
+        // copy tiles tb .. tb+nt-1 (16 records x 64 B each) into LDS; thread e
+        // of the block copies 16-byte groups e, e + 256, ...; a wave's 64 lanes
+        // land on 64 consecutive LDS slots
+        for (int e = threadIdx.x; e < nt * 64; e += 256) {
+            const uint32_t gidx = (uint32_t)tb * 64u + (uint32_t)e;
+            if (gidx < nrec4)
+                __builtin_amdgcn_global_load_lds((const FF_GLOBAL void*)(rec + gidx),
+                                                 (__attribute__((address_space(3))) void*)&tiles[e - lane], 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        // full tiles two at a time: key = (score << 11) | (2047 - local tile),
+        // one v_lshl_or per score and one v_max3 per two scores
+        const int tfull = min(tb + nt, N >> 4);
+        int t = tb;
+        for (; t + 1 < tfull; t += 2) {
+            const v4i B0 = tiles[(uint32_t)(t - tb) * 64u + lane_off];
+            const v4i B1 = tiles[(uint32_t)(t - tb) * 64u + 64u + lane_off];
+            const uint32_t tl0 = (uint32_t)(2047 - (t - t0)), tl1 = tl0 - 1u;
 #pragma unroll
-        for (int mq = 0; mq < MQ; ++mq) {
-            const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
-            const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
+            for (int mq = 0; mq < MQ; ++mq) {
+                const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
+                const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k0 = (int)(((uint32_t)acc0[i] << 11) | tl0);
-                const int k1 = (int)(((uint32_t)acc1[i] << 11) | tl1);
-                best[mq][i] = max(best[mq][i], max(k0, k1));
+                for (int i = 0; i < 4; ++i) {
+                    const int k0 = (int)(((uint32_t)acc0[i] << 11) | tl0);
+                    const int k1 = (int)(((uint32_t)acc1[i] << 11) | tl1);
+                    best[mq][i] = max(best[mq][i], max(k0, k1));
+                }
             }
         }
-    }
-    // at most one remaining tile, possibly the ragged last one of the plane
-    for (; t < t1; ++t) {
-        const int n = t * 16 + m;
-        const bool nvalid = n < N;
-        const v4i B = nvalid ? rec[(size_t)n * 4 + g] : zero;
-        const uint32_t tl = (uint32_t)(2047 - (t - t0));
+        // remaining tile of the chunk, possibly the ragged last one of the plane
+        for (; t < tb + nt; ++t) {
+            const bool nvalid = t * 16 + m < N;
+            const v4i B = tiles[(uint32_t)(t - tb) * 64u + lane_off];
+            const uint32_t tl = (uint32_t)(2047 - (t - t0));
 #pragma unroll
-        for (int mq = 0; mq < MQ; ++mq) {
-            const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
+            for (int mq = 0; mq < MQ; ++mq) {
+                const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | tl) : INT32_MIN;
-                best[mq][i] = max(best[mq][i], key);
+                for (int i = 0; i < 4; ++i) {
+                    const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | tl) : INT32_MIN;
+                    best[mq][i] = max(best[mq][i], key);
+                }
             }
         }
+        __syncthreads();                                         // chunk consumed before it is overwritten
     }
+    if (qbase >= Q) return;
 #pragma unroll
     for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
@@ -923,7 +946,7 @@ void launch_seed_nn(const PairDev* d, int npairs, int level, int stride, int max
     constexpr int MQ = 4;
     const int qwaves = (maxQ + 16 * MQ - 1) / (16 * MQ);
     const int ntiles = (maxN + 15) / 16;
-    int tps = 64;
+    int tps = 128;
     int splits = (ntiles + tps - 1) / tps;
     if (splits > 1024) {
         splits = 1024;

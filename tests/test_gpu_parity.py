@@ -205,6 +205,39 @@ def test_periodic_texture_seed_ties(torch, ffm, orc):
     _run_pair(torch, ffm, orc, i1, i2, p, "periodic texture")
 
 
+@pytest.mark.parametrize("kind", ["kitti", "periodic"])
+def test_seed_search_full_resolution_sampled(torch, ffm, orc, kind):
+    """Seed search over a whole 1242x375 level (levels = 1: Q = 51750 seeds
+    against N = 465750 pixels, hundreds of database splits and LDS chunks),
+    in the launch configuration the benchmark times; sampled seeds, the
+    first and last ones included, against the oracle's one-query search.
+    The periodic image makes most coarsest descriptors repeat, so ties
+    cross split boundaries."""
+    if kind == "kitti":
+        i1, i2, _ = synth.config1(seed=11)
+    else:
+        rng = np.random.default_rng(23)
+        tile = rng.integers(0, 256, size=(8, 8), dtype=np.uint8)
+        i1 = np.tile(tile, (47, 156))[:375, :1242].copy()
+        i2 = np.roll(i1, (3, 5), axis=(0, 1)).copy()
+    p = _prm(orc, levels=1)
+    m = _matcher(ffm, p)
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    D = [orc.descriptors(orc.gray(x)) for x in (i1, i2)]
+    rng = np.random.default_rng(24)
+    for d in (0, 1):
+        say("seed search full resolution", kind, "dir", d, "shape", i1.shape)
+        s = m.debug_stage(a, b, ffm.STAGE_SEEDS, dir=d).cpu().numpy()
+        nsy, nsx = s.shape
+        Q = nsy * nsx
+        qs = np.unique(np.concatenate([np.arange(70), np.arange(Q - 70, Q),
+                                       rng.integers(0, Q, size=120)]))
+        for q in qs:
+            y, x = (q // nsx) * 3, (q % nsx) * 3
+            assert s.reshape(-1)[q] == orc.nearest(D[d][y, x], D[1 - d]), (kind, d, int(q))
+    m.close()
+
+
 def test_identical_frames_zero_flow(torch, ffm, orc):
     rng = np.random.default_rng(22)
     img = synth._to_u8(synth.noise_texture(rng, 96, 160))

@@ -156,6 +156,24 @@ def test_seed_nn_ties_go_to_lowest_index(orc):
     assert idx[0, 1] == 0                  # all-zero query: every zero entry ties
 
 
+def test_nearest_single_query_matches_brute_force(orc):
+    rng = np.random.default_rng(6)
+    DB = rng.integers(-5, 6, size=(9, 23, 16), dtype=np.int8)     # many near-ties
+    db = DB.reshape(-1, 16).astype(np.int64)
+    for _ in range(40):
+        a = rng.integers(-6, 7, size=16, dtype=np.int8)
+        dist = ((a.astype(np.int64)[None] - db) ** 2).sum(-1)
+        assert orc.nearest(a, DB) == int(np.argmin(dist))
+    DB[4, 7] = DB[2, 3] = DB[8, 22] = 3                          # exact matches: lowest wins
+    assert orc.nearest(np.full(16, 3, np.int8), DB) == 2 * 23 + 3
+    # per-seed agreement with the plane search
+    DA = rng.integers(-5, 6, size=(9, 23, 16), dtype=np.int8)
+    idx = orc.seed_nn(DA, DB, 4)
+    for j in range(idx.shape[0]):
+        for i in range(idx.shape[1]):
+            assert orc.nearest(DA[4 * j, 4 * i], DB) == idx[j, i]
+
+
 # ---------------------------------------------------------------- Philox --
 def _kat():
     rows = []
