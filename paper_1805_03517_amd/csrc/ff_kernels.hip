@@ -33,6 +33,7 @@ typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef FF_GLOBAL const uint8_t gcu8;
 typedef FF_GLOBAL const u32x4 gcu4;
 typedef FF_GLOBAL i32x2 gi2;
+typedef __attribute__((address_space(3))) i32x2 li2;
 
 __device__ __forceinline__ uint4 ld16(gcu8* p)
 {
@@ -97,6 +98,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // (2,3) for odd j.  All trial costs are gathered first (independent loads),
 // then selected in trial order with a strict '<', which equals the
 // sequential rule because a trial equal to the running best costs the same.
+// A trial with a zero offset repeats v0, whose cost bounds the running best
+// from above, so it can never be taken and is not evaluated.
 // `cost(flow)` evaluates one trial (a global gather, or an LDS read when the
 // caller staged the target neighbourhood).
 template <int RC, typename CostFn>
@@ -117,8 +120,9 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, int W, 
             const uint32_t uy = (j & 1) ? u.w : u.y;
             const int r = RC >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
-            cand[j] = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            e[j] = cost(cand[j]);
+            const int dx = (int)(ux % span) - r, dy = (int)(uy % span) - r;
+            cand[j] = pack_flow(vx + dx, vy + dy);
+            e[j] = (dx | dy) != 0 ? cost(cand[j]) : kInf;        // zero offset: never selected
         }
 #pragma unroll
         for (int j = 0; j < JC; ++j)
@@ -131,8 +135,9 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, int W, 
             const uint32_t uy = (j & 1) ? u.w : u.y;
             const int r = sc.radius >> j;
             const uint32_t span = 2u * (uint32_t)r + 1u;
-            const uint32_t c = pack_flow(vx + (int)(ux % span) - r, vy + (int)(uy % span) - r);
-            const int32_t ej = cost(c);
+            const int dx = (int)(ux % span) - r, dy = (int)(uy % span) - r;
+            const uint32_t c = pack_flow(vx + dx, vy + dy);
+            const int32_t ej = (dx | dy) != 0 ? cost(c) : kInf;
             if (ej < bc) { bc = ej; bf = c; }
         }
     }
@@ -503,8 +508,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // order and the selection rule are those of random_search().
 template <int RC, bool COL, int CH>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
-                                                    gi2* __restrict__ S, int W, int H, int len, int line,
-                                                    int lane, bool fwd, bool rs, uint32_t level, uint32_t ctr2,
+                                                    const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
+                                                    bool lio, li2* lline, int W, int H, int len, int line, int lane,
+                                                    bool fwd, bool rs, uint32_t level, uint32_t ctr2,
                                                     const SearchConst& sc)
 {
     constexpr int WIN = 64 * CH;
@@ -520,7 +526,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
         for (int c = 0; c < CH; ++c) {
             const int p = w0 + 64 * c + lane;
             const bool valid = p < len;
-            const i32x2 st = valid ? S[p] : i32x2{0, kInf};
+            const i32x2 st = !valid ? i32x2{0, kInf} : lio ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
             A[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
             F[c] = (uint32_t)st.x;
             C[c] = st.y;
@@ -547,7 +553,8 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int32_t e = ((pin[c] >> j) & 1u) ? sad16(pa[c], pdesc[c][j]) : kInf;
                 if (e < bc) { bc = e; bf = pcand[c][j]; }
             }
-            S[p] = i32x2{(int)bf, bc};
+            if (lio) lline[p] = i32x2{(int)bf, bc};
+            else S[p] = i32x2{(int)bf, bc};
         }
     };
 
@@ -631,7 +638,9 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     const int qdx = (int)(ux % span) - r, qdy = (int)(uy % span) - r;
                     pcand[c][j] = pack_flow(vx + qdx, vy + qdy);
                     const int qx = x + flow_x(pcand[c][j]), qy = y + flow_y(pcand[c][j]);
-                    const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H;
+                    // a zero offset repeats the swept flow, whose cost is the
+                    // running best's upper bound: never selected, not gathered
+                    const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H && (qdx | qdy) != 0;
                     pin[c] |= in ? (1u << j) : 0u;
                     pdesc[c][j] = in ? ld16(DB + pix<COL>(qx, qy, W, H) * 16) : make_uint4(0, 0, 0, 0);
                 }
@@ -642,7 +651,10 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
-                if (p < len) S[p] = i32x2{(int)h[c], le[c] < c0[c] ? le[c] : c0[c]};
+                if (p >= len) continue;
+                const int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
+                if (lio) lline[p] = i32x2{(int)h[c], bc};
+                else S[p] = i32x2{(int)h[c], bc};
             }
         }
 #pragma unroll
@@ -668,7 +680,7 @@ struct StageDims {
 
 template <int RC, bool COL, int CH, int WPB, bool STG>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
-                                                         int iter, int upto, SearchConst sc)
+                                                         int iter, int upto, SearchConst sc, int xw)
 {
     const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int pd = lb / gridDim.x, bx = lb % gridDim.x;
@@ -682,7 +694,12 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const int line = line0 + wave;
     if (line0 >= nlines) return;                                 // whole block idle: uniform
     const bool active = line < nlines;
-    if (!STG && !active) return;
+    // column phase in LDS (xw): the block copies its WPB columns of the
+    // row-major state into LDS, both passes read and write them there, and
+    // the block stores them back row-major; otherwise the first pass reads
+    // the row-major state in place and the passes write stateT
+    const bool xwk = COL && xw;
+    if (!STG && !active && !xwk) return;
     gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
     gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
@@ -694,6 +711,18 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     __shared__ uint4 region[STG ? SD::CAP : 1];
     __shared__ int sample[2][WPB][2];                            // per parity: a flow sample (i, j) per line
     __shared__ int sample_ok[2][WPB];
+    extern __shared__ i32x2 lbuf_[];                             // xw: WPB lines x len
+    li2* const lbuf = (li2*)lbuf_;
+    li2* const lline = lbuf + wave * len;
+    if (xwk) {
+        const gi2* __restrict__ src = (const gi2*)L.state[dir];
+        const int nl = min(WPB, nlines - line0);
+        for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
+            const int k = e % WPB, p = e / WPB;
+            if (k < nl) lbuf[k * len + p] = src[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)];
+        }
+        __syncthreads();
+    }
     int gw = 0;                                                  // windows staged so far (slot parity)
 
     for (int pass = 0; pass < 2; ++pass) {
@@ -710,8 +739,14 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             rs_pass = fwd ? 1 : 2;
         }
         const uint32_t ctr2 = ((uint32_t)iter << 2) | rs_pass;
+        // the column phase's first pass reads the row-major state in place
+        const gi2* __restrict__ Sin = (COL && fwd) ? (const gi2*)L.state[dir] + line : S;
+        const int sstr = (COL && fwd) ? W : 1;
+
         if constexpr (!STG && RC > 0 && CH <= 2) {
-            line_pass_pipelined<RC, COL, CH>(DA, DB, S, W, H, len, line, lane, fwd, rs, (uint32_t)level, ctr2, sc);
+            if (active)
+                line_pass_pipelined<RC, COL, CH>(DA, DB, Sin, sstr, S, xwk, lline, W, H, len, line, lane, fwd, rs,
+                                                 (uint32_t)level, ctr2, sc);
             continue;
         }
         uint32_t carry = 0;
@@ -725,7 +760,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = active && p < len;
-                const i32x2 st = valid ? S[p] : i32x2{0, kInf};
+                const i32x2 st = !valid ? i32x2{0, kInf} : xwk ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
                 a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
                 f0[c] = (uint32_t)st.x;
                 c0[c] = st.y;
@@ -846,8 +881,19 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                           [&](uint32_t f) { return cost_at<COL>(DB, W, H, x, y, f, ac); });
                     }
                 }
-                S[p] = i32x2{(int)bf, bc};
+                if (xwk) lline[p] = i32x2{(int)bf, bc};
+                else S[p] = i32x2{(int)bf, bc};
             }
+        }
+    }
+    if (xwk) {
+        // WPB adjacent columns: for every row, WPB consecutive state entries
+        __syncthreads();
+        gi2* __restrict__ dst = (gi2*)L.state[dir];
+        const int nl = min(WPB, nlines - line0);
+        for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
+            const int k = e % WPB, p = e / WPB;
+            if (k < nl) dst[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)] = lbuf[k * len + p];
         }
     }
 }
@@ -961,21 +1007,30 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
 {
     hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
 }
+// The column phase's cross write holds WPB lines of results in LDS: used
+// when they fit in 64 KiB (columns up to 1024 px at 8 lines per block).
+bool line_cross_write(int wpb, int maxlen)
+{
+    return (size_t)wpb * (size_t)maxlen * sizeof(int2) <= 65536;
+}
+
 template <int RC, bool COL, int CH, int WPB, bool STG>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
-                   hipStream_t st)
+                   int maxlen, hipStream_t st)
 {
+    const int xw = COL && line_cross_write(WPB, maxlen) ? 1 : 0;
+    const size_t dyn = xw ? (size_t)WPB * maxlen * sizeof(int2) : 0;
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
-                       dim3(64 * WPB), 0, st, d, level, iter, upto, sc);
+                       dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw);
 }
 
 template <int RC, bool COL>
 bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
-                    const SearchConst& sc, int nlines, hipStream_t st)
+                    const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
 {
 #define FF_LINE_CASE(C, B, G)                                                                 \
     if (ch == C && wpb == B && stg == G) {                                                    \
-        launch_line_t<RC, COL, C, B, G != 0>(d, npairs, level, iter, upto, sc, nlines, st);  \
+        launch_line_t<RC, COL, C, B, G != 0>(d, npairs, level, iter, upto, sc, nlines, maxlen, st); \
         return true;                                                                          \
     }
     FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
@@ -992,14 +1047,17 @@ bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int 
 // random search; supported: stg 0 with ch in {1, 2, 4, 8} and wpb in {2, 4, 8}
 // (ch <= 2 runs the software-pipelined pass at radius 16); stg 1 with
 // (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false otherwise.
+// nlines / maxlen: the batch's largest line count and line length.  The
+// column phase reads the row-major state and, when line_cross_write()
+// allows it, also writes it (otherwise its result stays in stateT).
 bool launch_line_phase(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
-                       int upto, const SearchConst& sc, int nlines, hipStream_t st)
+                       int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
 {
     if (sc.radius == 16)
-        return col ? launch_line_rc<16, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st)
-                   : launch_line_rc<16, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st);
-    return col ? launch_line_rc<0, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st)
-               : launch_line_rc<0, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, st);
+        return col ? launch_line_rc<16, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
+                   : launch_line_rc<16, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+    return col ? launch_line_rc<0, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
+               : launch_line_rc<0, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

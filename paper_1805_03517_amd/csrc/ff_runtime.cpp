@@ -30,7 +30,9 @@ void launch_desc(const PairDev*, int, int, int, int, hipStream_t);
 void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, hipStream_t);
-bool launch_line_phase(bool, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, hipStream_t);
+bool launch_line_phase(bool, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, int,
+                       hipStream_t);
+bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
@@ -407,12 +409,14 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             const bool last = stop_here && stop.st.iter == t;
             const int upto = last ? stop.st.step : 7;
             FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], d, n, l, t,
-                                                std::min(upto, 3), sc, D.maxH[l], st));
+                                                std::min(upto, 3), sc, D.maxH[l], D.maxW[l], st));
             if (upto >= 4) {
-                FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 1, D.maxW[l], D.maxH[l], st));
+                // the column phase reads the row-major state; its result comes
+                // back row-major when the cross write applies, else from stateT
                 FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], d, n, l, t, upto, sc,
-                                                    D.maxW[l], st));
-                FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
+                                                    D.maxW[l], D.maxH[l], st));
+                if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
+                    FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
             }
             if (last) {
                 FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8,
