@@ -145,23 +145,56 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, int W, 
 
 // ------------------------------------------------------------- ingest ---
 // Level-0 luma of both images: Y = (77 R + 150 G + 29 B + 128) >> 8, C = 1
-// copies.  grid (pixels / 256, 2 * pairs).
+// copies.  16 pixels per thread: 48 (or 16) input bytes in 16-byte loads
+// when the image is 16-byte aligned, one 16-byte store; the plane's ragged
+// end and unaligned images go byte by byte.  grid (pixels / 4096, 2 * pairs).
+__device__ __forceinline__ uint32_t luma4(const uint32_t* w, int k0)
+{
+    // pixels k0 .. k0+3 of a 48-byte group held as 12 little-endian words
+    uint32_t out = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int j = 3 * (k0 + k);
+        const uint32_t r = (w[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const uint32_t g = (w[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xFFu;
+        const uint32_t b = (w[(j + 2) >> 2] >> (8 * ((j + 2) & 3))) & 0xFFu;
+        out |= ((77u * r + 150u * g + 29u * b + 128u) >> 8) << (8 * k);
+    }
+    return out;
+}
+
 __global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int img = blockIdx.y & 1;
     const int n = P.lv[0].W * P.lv[0].H;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 16;
+    if (i0 >= n) return;
     const uint8_t* src = P.img[img];
-    uint8_t v;
-    if (P.C == 3) {
-        const uint8_t* p = src + (size_t)i * 3;
-        v = (uint8_t)((77u * p[0] + 150u * p[1] + 29u * p[2] + 128u) >> 8);
-    } else {
-        v = src[i];
+    uint8_t* dst = P.lv[0].gray[img];
+    if (i0 + 16 <= n && ((uintptr_t)src & 15u) == 0) {
+        u32x4 o;
+        if (P.C == 3) {
+            gcu4* s4 = (gcu4*)(src + (size_t)i0 * 3);
+            const u32x4 a = s4[0], b = s4[1], c = s4[2];
+            const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+            o = u32x4{luma4(w, 0), luma4(w, 4), luma4(w, 8), luma4(w, 12)};
+        } else {
+            o = *(gcu4*)(src + i0);
+        }
+        *(FF_GLOBAL u32x4*)(dst + i0) = o;
+        return;
     }
-    P.lv[0].gray[img][i] = v;
+    for (int i = i0; i < min(i0 + 16, n); ++i) {
+        uint8_t v;
+        if (P.C == 3) {
+            const uint8_t* p = src + (size_t)i * 3;
+            v = (uint8_t)((77u * p[0] + 150u * p[1] + 29u * p[2] + 128u) >> 8);
+        } else {
+            v = src[i];
+        }
+        dst[i] = v;
+    }
 }
 
 // One pyramid step: 2x2 box mean rounded half up, floor dimensions.
@@ -183,11 +216,23 @@ __global__ __launch_bounds__(256) void k_down2(const PairDev* __restrict__ pairs
 // 16 Walsh-Hadamard coefficients of the 8x8 patch at every pixel (Sec. 3.1),
 // separable: the four lowest-sequency Walsh functions on 8 samples are
 // constant on sample pairs, so a 1-D transform is 4 pair sums and one
-// 4-point butterfly.  A block covers 64 x 16 outputs; its 71 x 23 input
-// window (replicated border), the 23 x 64 row transforms and the finished
-// descriptors live in LDS.  Written twice: row-major (lanes along x) and
-// column-major (lanes along y), both coalesced.
-constexpr int kDescTX = 64, kDescTY = 16;
+// 4-point butterfly.  A block covers 64 x 32 outputs.  Its 71 x 39 input
+// window (replicated border) and the 39 x 64 row transforms (4 x int16) live
+// in LDS; thread (c, g) takes column c, rows 8g .. 8g+7, and runs the column
+// transform on packed int16 pairs (every partial sum stays within 16 320):
+// 15 row transforms give the 14 vertical pair sums its 8 outputs share.
+// Written row-major straight from registers (lanes along x) and
+// column-major through LDS (lanes along y), both coalesced.
+constexpr int kDescTX = 64, kDescTY = 32;
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t desc_word(s16x2 lo, s16x2 hi, uint32_t bias)
+{
+    // floor(c / 64) of the four coefficients, low bytes packed, biased by +128
+    // except the DC byte (already 0..255)
+    const s16x2 ql = lo >> (short)6, qh = hi >> (short)6;
+    return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, qh), __builtin_bit_cast(uint32_t, ql), 0x06040200u) ^ bias;
+}
 
 __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs, int level)
 {
@@ -197,57 +242,92 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
     const int W = L.W, H = L.H;
     const int x0 = blockIdx.x * kDescTX, y0 = blockIdx.y * kDescTY;
     if (x0 >= W || y0 >= H) return;
-    __shared__ uint8_t tile[kDescTY + 7][kDescTX + 8];
-    __shared__ int16_t rowt[kDescTY + 7][kDescTX][4];
-    const uint8_t* src = L.gray[img];
-    for (int i = threadIdx.x; i < (kDescTY + 7) * (kDescTX + 7); i += 256) {
+    constexpr int TR = kDescTY + 7;                              // input rows
+    __shared__ union {
+        struct {
+            uint8_t tile[TR][kDescTX + 8];                      // 39 x 72 bytes (8-byte multiple)
+            uint2 rowt[TR][kDescTX];                            // 4 x int16 row transforms
+        } in;
+        uint4 res[kDescTY / 2][kDescTX + 1];                    // half of the finished descriptors
+    } sm;
+    // input window: all loads issued before the first LDS write
+    gcu8* __restrict__ src = (gcu8*)L.gray[img];
+    constexpr int NT = TR * (kDescTX + 7), NI = (NT + 255) / 256;
+    uint8_t v[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
         const int r = i / (kDescTX + 7), c = i % (kDescTX + 7);
         const int gy = min(max(y0 - 3 + r, 0), H - 1);
         const int gx = min(max(x0 - 3 + c, 0), W - 1);
-        tile[r][c] = src[(size_t)gy * W + gx];
+        v[k] = i < NT ? src[(uint32_t)gy * (uint32_t)W + (uint32_t)gx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NT) sm.in.tile[i / (kDescTX + 7)][i % (kDescTX + 7)] = v[k];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < (kDescTY + 7) * kDescTX; i += 256) {
+#pragma unroll
+    for (int k = 0; k < (TR * kDescTX + 255) / 256; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= TR * kDescTX) break;
         const int r = i / kDescTX, c = i % kDescTX;
-        const int q0 = tile[r][c] + tile[r][c + 1], q1 = tile[r][c + 2] + tile[r][c + 3];
-        const int q2 = tile[r][c + 4] + tile[r][c + 5], q3 = tile[r][c + 6] + tile[r][c + 7];
-        rowt[r][c][0] = (int16_t)(q0 + q1 + q2 + q3);
-        rowt[r][c][1] = (int16_t)(q0 + q1 - q2 - q3);
-        rowt[r][c][2] = (int16_t)(q0 - q1 - q2 + q3);
-        rowt[r][c][3] = (int16_t)(q0 - q1 + q2 - q3);
+        const uint8_t* t = &sm.in.tile[r][c];
+        const int q0 = t[0] + t[1], q1 = t[2] + t[3], q2 = t[4] + t[5], q3 = t[6] + t[7];
+        const int a = q0 + q1, b = q2 + q3, d = q0 - q1, e = q2 - q3;
+        // sequency order: (a + b, a - b, d - e, d + e)
+        sm.in.rowt[r][c] = make_uint2(((uint32_t)(a + b) & 0xFFFFu) | ((uint32_t)(a - b) << 16),
+                                      ((uint32_t)(d - e) & 0xFFFFu) | ((uint32_t)(d + e) << 16));
     }
     __syncthreads();
-    __shared__ uint4 res[kDescTY][kDescTX];
-    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {
-        const int c = i % kDescTX, r = i / kDescTX;
-        uint32_t words[4] = {0, 0, 0, 0};
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    // vertical pair sums P_k = rowt[8g + k] + rowt[8g + k + 1], k = 0 .. 13,
+    // as (v0, v1) and (v2, v3) packed pairs
+    s16x2 pl[14], ph[14];
+    {
+        uint2 prev = sm.in.rowt[8 * g][c];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int p0 = rowt[r][c][v] + rowt[r + 1][c][v], p1 = rowt[r + 2][c][v] + rowt[r + 3][c][v];
-            const int p2 = rowt[r + 4][c][v] + rowt[r + 5][c][v], p3 = rowt[r + 6][c][v] + rowt[r + 7][c][v];
-            const int cu[4] = {p0 + p1 + p2 + p3, p0 + p1 - p2 - p3, p0 - p1 - p2 + p3, p0 - p1 + p2 - p3};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = 4 * u + v;
-                // floor(c / 64) as int8, DC shifted by -128; stored biased (+128)
-                const int d = (cu[u] >> 6) + (k == 0 ? 0 : 128);
-                words[k >> 2] |= (uint32_t)(d & 0xFF) << (8 * (k & 3));
-            }
+        for (int k = 0; k < 14; ++k) {
+            const uint2 nxt = sm.in.rowt[8 * g + k + 1][c];
+            pl[k] = __builtin_bit_cast(s16x2, prev.x) + __builtin_bit_cast(s16x2, nxt.x);
+            ph[k] = __builtin_bit_cast(s16x2, prev.y) + __builtin_bit_cast(s16x2, nxt.y);
+            prev = nxt;
         }
-        res[r][c] = make_uint4(words[0], words[1], words[2], words[3]);
     }
-    __syncthreads();
+    uint4 out[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        // column butterfly over the pair sums at rows i, i+2, i+4, i+6
+        const s16x2 al = pl[i] + pl[i + 2], bl = pl[i + 4] + pl[i + 6];
+        const s16x2 dl = pl[i] - pl[i + 2], el = pl[i + 4] - pl[i + 6];
+        const s16x2 ah = ph[i] + ph[i + 2], bh = ph[i + 4] + ph[i + 6];
+        const s16x2 dh = ph[i] - ph[i + 2], eh = ph[i + 4] - ph[i + 6];
+        out[i] = make_uint4(desc_word(al + bl, ah + bh, 0x80808000u), desc_word(al - bl, ah - bh, 0x80808080u),
+                            desc_word(dl - el, dh - eh, 0x80808080u), desc_word(dl + el, dh + eh, 0x80808080u));
+    }
+    const int x = x0 + c;
     uint8_t* dst = L.desc[img];
-    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {         // row-major: lanes along x
-        const int c = i % kDescTX, r = i / kDescTX;
-        const int x = x0 + c, y = y0 + r;
-        if (x < W && y < H) *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = res[r][c];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
+        const int y = y0 + 8 * g + i;
+        if (x < W && y < H) *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = out[i];
     }
     uint8_t* dstT = L.descT[img];
-    for (int i = threadIdx.x; i < kDescTY * kDescTX; i += 256) {         // column-major: lanes along y
-        const int r = i % kDescTY, c = i / kDescTY;
-        const int x = x0 + c, y = y0 + r;
-        if (x < W && y < H) *reinterpret_cast<uint4*>(dstT + ((size_t)x * H + y) * 16) = res[r][c];
+    for (int half = 0; half < 2; ++half) {                       // column-major, 16 rows at a time
+        __syncthreads();                                         // row transforms / previous half consumed
+        if ((g >> 1) == half) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sm.res[8 * (g & 1) + i][c] = out[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {                            // lanes along y: 16 rows x 4 columns a wave
+            const int i = threadIdx.x + 256 * k;
+            const int r = i % 16, cc = i / 16;
+            const int xx = x0 + cc, yy = y0 + 16 * half + r;
+            if (xx < W && yy < H) *reinterpret_cast<uint4*>(dstT + ((size_t)xx * H + yy) * 16) = sm.res[r][cc];
+        }
     }
 }
 
@@ -929,29 +1009,58 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
 // Forward-backward check at level 0 (Sec. 3.1, threshold epsilon): p is kept
 // when its match and the match of q = p + F(p) are valid and
 // |F(p) + B(q)|^2 <= eps^2.  Writes the caller's flow / cost / mask.
+__device__ __forceinline__ uint32_t fb_mask(const gi2* __restrict__ other, int W, int x, int y, i32x2 s, int eps2)
+{
+    if (s.y == kInf) return 0;
+    const uint32_t F = (uint32_t)s.x;
+    const int qx = x + flow_x(F), qy = y + flow_y(F);
+    const i32x2 t = other[(uint32_t)qy * (uint32_t)W + (uint32_t)qx];
+    if (t.y == kInf) return 0;
+    const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
+    return ex * ex + ey * ey <= eps2 ? 1u : 0u;
+}
+
+// Four consecutive pixels per thread: 32 bytes of state in two 16-byte
+// loads, the four flows, costs and mask bytes in one store each when the
+// output buffers are 16- and 4-byte aligned; otherwise pixel by pixel.
+// grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
     const LevelDev& L = P.lv[0];
-    const int W = L.W, H = L.H;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= W * H) return;
-    const int2 s = L.state[dir][i];
-    const uint32_t F = (uint32_t)s.x;
-    uint8_t m = 0;
-    if (s.y != kInf) {
-        const int x = i % W, y = i / W;
-        const int qx = x + flow_x(F), qy = y + flow_y(F);
-        const int2 t = L.state[dir ^ 1][(size_t)qy * W + qx];
-        if (t.y != kInf) {
-            const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
-            m = (ex * ex + ey * ey <= eps2) ? 1 : 0;
+    const int W = L.W, n = L.W * L.H;
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    const gi2* __restrict__ own = (const gi2*)L.state[dir];
+    const gi2* __restrict__ other = (const gi2*)L.state[dir ^ 1];
+    uint32_t* fl = reinterpret_cast<uint32_t*>(P.flow[dir]);
+    int32_t* co = P.cost[dir];
+    uint8_t* mk = P.mask[dir];
+    int y = i0 / W, x = i0 - y * W;
+    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0) {
+        const u32x4 s01 = *(gcu4*)(own + i0), s23 = *(gcu4*)(own + i0 + 2);
+        const i32x2 s[4] = {i32x2{(int)s01.x, (int)s01.y}, i32x2{(int)s01.z, (int)s01.w},
+                            i32x2{(int)s23.x, (int)s23.y}, i32x2{(int)s23.z, (int)s23.w}};
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m |= fb_mask(other, W, x, y, s[k], eps2) << (8 * k);
+            if (++x == W) { x = 0; ++y; }
         }
+        if (fl) *(FF_GLOBAL u32x4*)(fl + i0) = u32x4{(uint32_t)s[0].x, (uint32_t)s[1].x, (uint32_t)s[2].x, (uint32_t)s[3].x};
+        if (co) *(FF_GLOBAL u32x4*)(co + i0) = u32x4{(uint32_t)s[0].y, (uint32_t)s[1].y, (uint32_t)s[2].y, (uint32_t)s[3].y};
+        if (mk) *(FF_GLOBAL uint32_t*)(mk + i0) = m;
+        return;
     }
-    if (P.flow[dir]) reinterpret_cast<uint32_t*>(P.flow[dir])[i] = F;
-    if (P.cost[dir]) P.cost[dir][i] = s.y;
-    if (P.mask[dir]) P.mask[dir][i] = m;
+    for (int i = i0; i < min(i0 + 4, n); ++i) {
+        const i32x2 st = own[i];
+        const uint32_t m = fb_mask(other, W, x, y, st, eps2);
+        if (fl) fl[i] = (uint32_t)st.x;
+        if (co) co[i] = st.y;
+        if (mk) mk[i] = (uint8_t)m;
+        if (++x == W) { x = 0; ++y; }
+    }
 }
 
 // ------------------------------------------------------------- debug ----
@@ -972,6 +1081,7 @@ __global__ void k_keys_to_index(const unsigned long long* __restrict__ keys, int
 
 void launch_gray(const PairDev* d, int npairs, int maxpx, hipStream_t st)
 {
+    maxpx = (maxpx + 15) / 16;                                   // threads of 16 pixels
     hipLaunchKernelGGL(k_gray, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
 }
 void launch_down2(const PairDev* d, int npairs, int level, int maxpx, hipStream_t st)
@@ -1067,7 +1177,7 @@ void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, i
 }
 void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fb, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, eps2);
+    hipLaunchKernelGGL(k_fb, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
 }
 void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, size_t n, hipStream_t st)
 {

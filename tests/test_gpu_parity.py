@@ -238,6 +238,40 @@ def test_seed_search_full_resolution_sampled(torch, ffm, orc, kind):
     m.close()
 
 
+@pytest.mark.parametrize("C", [1, 3])
+def test_unaligned_buffers(torch, ffm, orc, C):
+    """Images starting at odd addresses and outputs that are only 4-byte
+    (flow, cost) or 1-byte (mask) aligned take the element-wise paths of the
+    ingest and output kernels; results are those of aligned buffers."""
+    W, H = 131, 67
+    rng = np.random.default_rng(25 + C)
+    i1, i2, _ = synth.translated_pair(rng, W, H, d=(3, -2))
+    if C == 3:
+        i1 = np.stack([i1, np.roll(i1, 1, 0), np.roll(i1, 2, 1)], -1)
+        i2 = np.stack([i2, np.roll(i2, 1, 0), np.roll(i2, 2, 1)], -1)
+    p = _prm(orc, levels=3)
+    m = _matcher(ffm, p)
+    n = i1.size
+    def odd_view(a):
+        buf = torch.zeros(n + 1, dtype=torch.uint8, device="cuda")
+        v = buf[1:].view(*a.shape)
+        v.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+        return v
+    a, b = odd_view(i1), odd_view(i2)
+    assert a.data_ptr() % 2 == 1
+    out = {}
+    for k, dt, shape, off in [("flow_f", torch.int16, (H, W, 2), 2), ("flow_b", torch.int16, (H, W, 2), 2),
+                              ("cost_f", torch.int32, (H, W), 1), ("cost_b", torch.int32, (H, W), 1),
+                              ("mask_f", torch.uint8, (H, W), 1), ("mask_b", torch.uint8, (H, W), 1)]:
+        cnt = int(np.prod(shape))
+        out[k] = torch.zeros(cnt + off, dtype=dt, device="cuda")[off:].view(*shape)
+    say("unaligned buffers C", C, "shape", i1.shape)
+    got = m.match(a, b, out=out)
+    torch.cuda.synchronize()
+    _compare_outputs(orc.match(i1, i2, p), got, f"unaligned C={C}")
+    m.close()
+
+
 def test_identical_frames_zero_flow(torch, ffm, orc):
     rng = np.random.default_rng(22)
     img = synth._to_u8(synth.noise_texture(rng, 96, 160))
