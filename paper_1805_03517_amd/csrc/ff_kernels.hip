@@ -589,7 +589,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 template <int RC, bool COL, int CH>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
-                                                    bool lio, li2* lline, int W, int H, int len, int line, int lane,
+                                                    bool lin, bool lout, li2* lline, int W, int H, int len, int line,
+                                                    int lane,
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
                                                     const SearchConst& sc)
 {
@@ -606,7 +607,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
         for (int c = 0; c < CH; ++c) {
             const int p = w0 + 64 * c + lane;
             const bool valid = p < len;
-            const i32x2 st = !valid ? i32x2{0, kInf} : lio ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
+            const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
             A[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
             F[c] = (uint32_t)st.x;
             C[c] = st.y;
@@ -633,7 +634,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int32_t e = ((pin[c] >> j) & 1u) ? sad16(pa[c], pdesc[c][j]) : kInf;
                 if (e < bc) { bc = e; bf = pcand[c][j]; }
             }
-            if (lio) lline[p] = i32x2{(int)bf, bc};
+            if (lout) lline[p] = i32x2{(int)bf, bc};
             else S[p] = i32x2{(int)bf, bc};
         }
     };
@@ -733,7 +734,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int p = w0 + 64 * c + lane;
                 if (p >= len) continue;
                 const int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
-                if (lio) lline[p] = i32x2{(int)h[c], bc};
+                if (lout) lline[p] = i32x2{(int)h[c], bc};
                 else S[p] = i32x2{(int)h[c], bc};
             }
         }
@@ -774,12 +775,16 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const int line = line0 + wave;
     if (line0 >= nlines) return;                                 // whole block idle: uniform
     const bool active = line < nlines;
-    // column phase in LDS (xw): the block copies its WPB columns of the
-    // row-major state into LDS, both passes read and write them there, and
-    // the block stores them back row-major; otherwise the first pass reads
-    // the row-major state in place and the passes write stateT
-    const bool xwk = COL && xw;
-    if (!STG && !active && !xwk) return;
+    // Lines' state in LDS between the passes (xw).  Column phase: the block
+    // copies its WPB columns of the row-major state into LDS, both passes
+    // read and write them there, and the block stores them back row-major
+    // (otherwise the first pass reads the row-major state in place and the
+    // passes write stateT).  Row phase: the first pass reads the state from
+    // global memory and leaves its result in LDS, the second pass reads it
+    // there and writes global memory.
+    const bool xwk = xw != 0;
+    const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
+    if (!STG && !active && !xwc) return;
     gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
     gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
@@ -794,7 +799,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     extern __shared__ i32x2 lbuf_[];                             // xw: WPB lines x len
     li2* const lbuf = (li2*)lbuf_;
     li2* const lline = lbuf + wave * len;
-    if (xwk) {
+    if (xwc) {
         const gi2* __restrict__ src = (const gi2*)L.state[dir];
         const int nl = min(WPB, nlines - line0);
         for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
@@ -822,10 +827,12 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         // the column phase's first pass reads the row-major state in place
         const gi2* __restrict__ Sin = (COL && fwd) ? (const gi2*)L.state[dir] + line : S;
         const int sstr = (COL && fwd) ? W : 1;
+        const bool lin = xwk && (COL || !fwd);
+        const bool lout = xwk && (COL || (fwd && upto >= 2));
 
         if constexpr (!STG && RC > 0 && CH <= 2) {
             if (active)
-                line_pass_pipelined<RC, COL, CH>(DA, DB, Sin, sstr, S, xwk, lline, W, H, len, line, lane, fwd, rs,
+                line_pass_pipelined<RC, COL, CH>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
                                                  (uint32_t)level, ctr2, sc);
             continue;
         }
@@ -840,7 +847,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = active && p < len;
-                const i32x2 st = !valid ? i32x2{0, kInf} : xwk ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
+                const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
                 a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
                 f0[c] = (uint32_t)st.x;
                 c0[c] = st.y;
@@ -961,12 +968,12 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                           [&](uint32_t f) { return cost_at<COL>(DB, W, H, x, y, f, ac); });
                     }
                 }
-                if (xwk) lline[p] = i32x2{(int)bf, bc};
+                if (lout) lline[p] = i32x2{(int)bf, bc};
                 else S[p] = i32x2{(int)bf, bc};
             }
         }
     }
-    if (xwk) {
+    if (xwc) {
         // WPB adjacent columns: for every row, WPB consecutive state entries
         __syncthreads();
         gi2* __restrict__ dst = (gi2*)L.state[dir];
@@ -1117,8 +1124,8 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
 {
     hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
 }
-// The column phase's cross write holds WPB lines of results in LDS: used
-// when they fit in 64 KiB (columns up to 1024 px at 8 lines per block).
+// A line phase keeps its WPB lines' state in LDS between its passes when
+// they fit in 64 KiB (lines up to 1024 px at 8 lines per block, 2048 px at 4).
 bool line_cross_write(int wpb, int maxlen)
 {
     return (size_t)wpb * (size_t)maxlen * sizeof(int2) <= 65536;
@@ -1128,7 +1135,7 @@ template <int RC, bool COL, int CH, int WPB, bool STG>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
                    int maxlen, hipStream_t st)
 {
-    const int xw = COL && line_cross_write(WPB, maxlen) ? 1 : 0;
+    const int xw = line_cross_write(WPB, maxlen) ? 1 : 0;
     const size_t dyn = xw ? (size_t)WPB * maxlen * sizeof(int2) : 0;
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
                        dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw);
