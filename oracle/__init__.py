@@ -58,6 +58,8 @@ def lib():
         l.ffo_descriptors.argtypes = [P, i, i, P]
         l.ffo_seed_nn.argtypes = [P, P, i, i, i, P]
         l.ffo_nearest.argtypes = [P, P, i]
+        l.ffo_fb_error.argtypes = [i, i, P, P, P, P, P]
+        l.ffo_sparsify.argtypes = [i, i, P, P, i, P]
         l.ffo_nearest.restype = ctypes.c_int32
         l.ffo_philox4x32_10.argtypes = [P, P, P]
         l.ffo_cost.argtypes = [P, P, i, i, i, i, i, i]
@@ -164,6 +166,30 @@ def random_search(DA, DB, flow, cst, level, it, pss, radius, seed):
     lib().ffo_random_search(_p(DA), _p(DB), W, H, level, it, pss, radius,
                             ctypes.c_uint64(seed), _p(f), _p(c))
     return f, c
+
+
+def fb_error(F, cF, B, cB) -> np.ndarray:
+    """Sec. 3.1 consistency error per pixel: |F(p) + B(p + F(p))|^2, INF
+    where either match is invalid."""
+    F = np.ascontiguousarray(F, dtype=np.int16)
+    B = np.ascontiguousarray(B, dtype=np.int16)
+    cF = np.ascontiguousarray(cF, dtype=np.int32)
+    cB = np.ascontiguousarray(cB, dtype=np.int32)
+    H, W = cF.shape
+    out = np.empty((H, W), np.int32)
+    lib().ffo_fb_error(W, H, _p(F), _p(cF), _p(B), _p(cB), _p(out))
+    return out
+
+
+def sparsify(mask, err, s: int) -> np.ndarray:
+    """Sec. 3.1 sparsification: per 3x3 block with >= s consistent matches,
+    keep the lowest-error one (lowest index on ties)."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    err = np.ascontiguousarray(err, dtype=np.int32)
+    H, W = mask.shape
+    out = np.empty((H, W), np.uint8)
+    lib().ffo_sparsify(W, H, _p(mask), _p(err), int(s), _p(out))
+    return out
 
 
 def match(img1: np.ndarray, img2: np.ndarray, prm: Params | None = None, trace=None):

@@ -370,6 +370,52 @@ static void consistency(int W, int H, int eps, const int16_t* F, const int32_t* 
         }
 }
 
+/* Consistency error (Sec. 3.1), the quantity the mask thresholds.       */
+void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
+                  const int16_t* B, const int32_t* cB, int32_t* err)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            int32_t e = FFO_INF;
+            if (cF[p] != FFO_INF) {
+                int qx = x + F[2 * p], qy = y + F[2 * p + 1];
+                size_t q = (size_t)qy * W + qx;
+                if (cB[q] != FFO_INF) {
+                    int ex = F[2 * p] + B[2 * q], ey = F[2 * p + 1] + B[2 * q + 1];
+                    e = ex * ex + ey * ey;
+                }
+            }
+            err[p] = e;
+        }
+}
+
+/* Sparsification (Sec. 3.1, s from Table 3): one kept match per 3x3 block
+ * holding at least s consistent matches -- the lowest consistency error,
+ * scanning the block in row-major order so the first minimum is the lowest
+ * linear index.                                                           */
+void ffo_sparsify(int W, int H, const uint8_t* mask, const int32_t* err, int s, uint8_t* keep)
+{
+    for (size_t p = 0; p < (size_t)W * H; ++p) keep[p] = 0;
+    for (int by = 0; by < H; by += 3)
+        for (int bx = 0; bx < W; bx += 3) {
+            int count = 0;
+            size_t best = 0;
+            int32_t best_e = FFO_INF;
+            for (int y = by; y < by + 3 && y < H; ++y)
+                for (int x = bx; x < bx + 3 && x < W; ++x) {
+                    size_t p = (size_t)y * W + x;
+                    if (!mask[p]) continue;
+                    ++count;
+                    if (count == 1 || err[p] < best_e) {
+                        best_e = err[p];
+                        best = p;
+                    }
+                }
+            if (count >= s) keep[best] = 1;
+        }
+}
+
 int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
               int W, int H, int C,
               int16_t* flow_f, int32_t* cost_f, uint8_t* mask_f,

@@ -74,6 +74,20 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
               int16_t* flow_b, int32_t* cost_b, uint8_t* mask_b,
               ffo_trace_fn trace, void* user);
 
+/* Consistency error of every pixel p (Sec. 3.1): with q = p + F(p), the
+ * squared length |F(p) + B(q)|^2 when both matches are valid (finite cost),
+ * FFO_INF otherwise.  The consistency mask is exactly err <= eps^2.       */
+void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
+                  const int16_t* B, const int32_t* cB, int32_t* err);
+
+/* Sparsification (Sec. 3.1; minimum matches s from Table 3): the image is
+ * cut into 3x3 blocks from the origin, the last column and row of blocks
+ * partial when W or H is not a multiple of 3.  A block that holds at least
+ * s consistent matches (mask = 1) keeps the one with the lowest consistency
+ * error, the lowest y*W + x among equals; every other pixel is dropped.
+ * keep is [H][W], 1 = kept match.                                         */
+void ffo_sparsify(int W, int H, const uint8_t* mask, const int32_t* err, int s, uint8_t* keep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -174,6 +174,84 @@ def test_nearest_single_query_matches_brute_force(orc):
             assert orc.nearest(DA[4 * j, 4 * i], DB) == idx[j, i]
 
 
+# ------------------------------------------------- consistency / sparse --
+def test_fb_error_worked_example(orc):
+    # q = p + F(p); err = |F(p) + B(q)|^2, INF when either match is invalid
+    F = np.array([[[1, 0], [0, 0], [-1, 0], [0, 0]]], np.int16)
+    cF = np.array([[10, orc.INF, 3, 7]], np.int32)
+    B = np.array([[[0, 0], [-1, 1], [0, 0], [2, 2]]], np.int16)
+    cB = np.array([[0, 2, 0, orc.INF]], np.int32)
+    err = orc.fb_error(F, cF, B, cB)
+    assert err.tolist() == [[1, orc.INF, 5, orc.INF]]
+
+
+@pytest.mark.parametrize("eps", [0, 1, 2, 7])
+def test_fb_error_thresholds_reproduce_the_mask(orc, eps):
+    """The consistency check keeps p iff its error is at most eps^2 (both
+    directions); the flows themselves do not depend on eps."""
+    i1, i2, _ = synth.config0()
+    r = orc.match(i1, i2, orc.params(levels=3, fb_eps=eps))
+    ef = orc.fb_error(r["flow_f"], r["cost_f"], r["flow_b"], r["cost_b"])
+    eb = orc.fb_error(r["flow_b"], r["cost_b"], r["flow_f"], r["cost_f"])
+    assert np.array_equal(r["mask_f"], (ef <= eps * eps).astype(np.uint8))
+    assert np.array_equal(r["mask_b"], (eb <= eps * eps).astype(np.uint8))
+    assert np.array_equal(ef == orc.INF, (r["cost_f"] == orc.INF) | (ef == orc.INF))
+    assert (ef[r["cost_f"] == orc.INF] == orc.INF).all()
+
+
+def _read_sparse_fixture():
+    lines = [l.strip() for l in open(os.path.join(HERE, "golden", "sparsify_3x3_example.txt"))]
+    rows = [l for l in lines if l and not l.startswith("#") and not l.startswith("s ")]
+    mask = np.array([[int(v) for v in r.split()] for r in rows[:5]], np.uint8)
+    err = np.array([[int(v) for v in r.split()] for r in rows[5:10]], np.int32)
+    kept = {}
+    for l in lines:
+        if l.startswith("s "):
+            head, _, tail = l.partition(":")
+            kept[int(head[2:])] = [tuple(int(v) for v in t.split(",")) for t in tail.split()]
+    return mask, err, kept
+
+
+def test_sparsify_worked_example(orc):
+    mask, err, kept = _read_sparse_fixture()
+    for s, pts in kept.items():
+        keep = orc.sparsify(mask, err, s)
+        got = sorted((int(x), int(y)) for y, x in np.argwhere(keep))
+        assert got == sorted(pts), (s, got)
+
+
+def _sparsify_by_sorting(mask, err, s):
+    """Brute force by another route: sort every match by (block, error,
+    index) and take the head of each block that has >= s members."""
+    H, W = mask.shape
+    ys, xs = np.nonzero(mask)
+    idx = ys * W + xs
+    blk = (ys // 3) * ((W + 2) // 3) + xs // 3
+    order = np.lexsort((idx, err[ys, xs], blk))
+    keep = np.zeros((H, W), np.uint8)
+    b_sorted = blk[order]
+    starts = np.flatnonzero(np.r_[True, b_sorted[1:] != b_sorted[:-1]])
+    counts = np.diff(np.r_[starts, len(order)])
+    for st, n in zip(starts, counts):
+        if n >= s:
+            k = order[st]
+            keep[ys[k], xs[k]] = 1
+    return keep
+
+
+def test_sparsify_matches_brute_force(orc):
+    rng = np.random.default_rng(9)
+    for (H, W) in [(3, 3), (5, 7), (1, 1), (2, 11), (16, 13), (30, 31)]:
+        for s in range(1, 11):
+            mask = (rng.random((H, W)) < 0.7).astype(np.uint8)
+            err = rng.integers(0, 4, size=(H, W)).astype(np.int32)      # many ties
+            keep = orc.sparsify(mask, err, s)
+            assert np.array_equal(keep, _sparsify_by_sorting(mask, err, s)), (H, W, s)
+            assert not (keep & (1 - mask)).any()
+            if s > 9:
+                assert not keep.any()
+
+
 # ---------------------------------------------------------------- Philox --
 def _kat():
     rows = []
