@@ -21,7 +21,11 @@
  *   - random search: radii R, R>>1, ..., 1 around the pre-pass flow, offsets
  *     from Philox4x32-10 at counter (y*W+x, level, iter<<2|pass, j>>1) and
  *     key (seed low, seed high), accepted on a strictly lower cost;
- *   - mask(p) = 1 iff both matches are valid and |F(p) + B(p + F(p))|^2 <= eps^2.
+ *   - mask(p) = 1 iff both matches are valid and |F(p) + B(p + F(p))|^2 <= eps^2;
+ *   - optionally (FF_SPARSIFY, Sec. 3.1 with s from Table 3): in every 3x3
+ *     block from the origin (partial at the borders) holding at least s
+ *     consistent matches, only the match with the lowest consistency error
+ *     |F(p) + B(p + F(p))|^2 is kept (the lowest y*W + x among equals).
  *
  * Memory: every pointer in ff_pair is DEVICE memory owned by the caller.
  * The handle owns its workspaces (pyramids, descriptors, search state, seed
@@ -53,7 +57,11 @@ typedef enum {
     FF_ERR_BUSY = 6          /* serving queue full                           */
 } ff_status;
 
-/* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 for KITTI). */
+/* flags */
+#define FF_SPARSIFY 1u      /* compute sparse_fwd / sparse_bwd (3x3-block selection) */
+
+/* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 and s = 7 for
+ * KITTI, epsilon = 7 and s = 4 for MPI Sintel). */
 typedef struct {
     int32_t  levels;        /* pyramid levels L, 1..8 (3 or 4 in the workloads)  */
     int32_t  seed_stride;   /* seed grid step at the coarsest level (3)          */
@@ -62,7 +70,9 @@ typedef struct {
     int32_t  fb_eps;        /* consistency threshold in px, 0..1024 (1)          */
     uint64_t seed;          /* random-search key                                 */
     uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
-    uint32_t flags;         /* reserved, must be 0                               */
+    uint32_t flags;         /* 0 or FF_SPARSIFY                                  */
+    int32_t  sparse_min;    /* s: matches a 3x3 block needs to keep one, 1..9
+                               (7); read only with FF_SPARSIFY                 */
 } ff_params;
 
 /* One image pair and its outputs.  Both frames are [H][W][C] uint8,
@@ -70,7 +80,12 @@ typedef struct {
  * min(W, H) >> (levels-1) >= 1.
  * flow_*: [H][W][2] int16 (dx, dy); cost_*: [H][W] int32 (INT32_MAX =
  * no valid match); mask_*: [H][W] uint8 (1 = consistent).  flow_fwd and
- * mask_fwd are required; every other output may be NULL.                 */
+ * mask_fwd are required; every other output may be NULL.
+ * fberr_*: [H][W] int32 consistency error |F(p) + B(p + F(p))|^2, INT32_MAX
+ * where either match is invalid (mask = fberr <= eps^2); written when not
+ * NULL.  sparse_*: [H][W] uint8, 1 = match kept by the 3x3-block
+ * sparsification; sparse_fwd is required with FF_SPARSIFY, and both must be
+ * NULL without it.  flow, cost and fberr buffers must be 4-byte aligned.  */
 typedef struct {
     const uint8_t* img1;
     const uint8_t* img2;
@@ -81,6 +96,10 @@ typedef struct {
     int16_t* flow_bwd;
     int32_t* cost_bwd;
     uint8_t* mask_bwd;
+    int32_t* fberr_fwd;
+    uint8_t* sparse_fwd;
+    int32_t* fberr_bwd;
+    uint8_t* sparse_bwd;
 } ff_pair;
 
 /* Create a handle on HIP device `device` (must be gfx950).  Copies *params. */

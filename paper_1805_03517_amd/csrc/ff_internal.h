@@ -43,6 +43,8 @@ struct PairDev {
     int16_t* flow[2];                // outputs (fwd, bwd); bwd entries may be null
     int32_t* cost[2];
     uint8_t* mask[2];
+    int32_t* fberr[2];               // consistency error (caller's buffer, or the workspace's when sparsifying)
+    uint8_t* sparse[2];              // 3x3-block selection (caller's); null = not computed
 };
 
 struct SearchConst {

@@ -1016,20 +1016,23 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
 // Forward-backward check at level 0 (Sec. 3.1, threshold epsilon): p is kept
 // when its match and the match of q = p + F(p) are valid and
 // |F(p) + B(q)|^2 <= eps^2.  Writes the caller's flow / cost / mask.
-__device__ __forceinline__ uint32_t fb_mask(const gi2* __restrict__ other, int W, int x, int y, i32x2 s, int eps2)
+// Consistency error |F(p) + B(q)|^2, q = p + F(p); INF when either match is
+// invalid (a finite cost means q lies inside the image).  mask = err <= eps^2.
+__device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, int x, int y, i32x2 s)
 {
-    if (s.y == kInf) return 0;
+    if (s.y == kInf) return kInf;
     const uint32_t F = (uint32_t)s.x;
     const int qx = x + flow_x(F), qy = y + flow_y(F);
     const i32x2 t = other[(uint32_t)qy * (uint32_t)W + (uint32_t)qx];
-    if (t.y == kInf) return 0;
+    if (t.y == kInf) return kInf;
     const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
-    return ex * ex + ey * ey <= eps2 ? 1u : 0u;
+    return ex * ex + ey * ey;
 }
 
 // Four consecutive pixels per thread: 32 bytes of state in two 16-byte
-// loads, the four flows, costs and mask bytes in one store each when the
-// output buffers are 16- and 4-byte aligned; otherwise pixel by pixel.
+// loads, the four flows, costs, errors and mask bytes in one store each when
+// the output buffers are 16- and 4-byte aligned; otherwise pixel by pixel.
+// The error plane is written when the table holds one.
 // grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2)
 {
@@ -1044,17 +1047,22 @@ __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, i
     uint32_t* fl = reinterpret_cast<uint32_t*>(P.flow[dir]);
     int32_t* co = P.cost[dir];
     uint8_t* mk = P.mask[dir];
+    int32_t* er = P.fberr[dir];
     int y = i0 / W, x = i0 - y * W;
-    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0) {
+    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0 &&
+        ((uintptr_t)er & 15u) == 0) {
         const u32x4 s01 = *(gcu4*)(own + i0), s23 = *(gcu4*)(own + i0 + 2);
         const i32x2 s[4] = {i32x2{(int)s01.x, (int)s01.y}, i32x2{(int)s01.z, (int)s01.w},
                             i32x2{(int)s23.x, (int)s23.y}, i32x2{(int)s23.z, (int)s23.w}};
         uint32_t m = 0;
+        int32_t e[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            m |= fb_mask(other, W, x, y, s[k], eps2) << (8 * k);
+            e[k] = fb_err(other, W, x, y, s[k]);
+            m |= (e[k] <= eps2 ? 1u : 0u) << (8 * k);
             if (++x == W) { x = 0; ++y; }
         }
+        if (er) *(FF_GLOBAL u32x4*)(er + i0) = u32x4{(uint32_t)e[0], (uint32_t)e[1], (uint32_t)e[2], (uint32_t)e[3]};
         if (fl) *(FF_GLOBAL u32x4*)(fl + i0) = u32x4{(uint32_t)s[0].x, (uint32_t)s[1].x, (uint32_t)s[2].x, (uint32_t)s[3].x};
         if (co) *(FF_GLOBAL u32x4*)(co + i0) = u32x4{(uint32_t)s[0].y, (uint32_t)s[1].y, (uint32_t)s[2].y, (uint32_t)s[3].y};
         if (mk) *(FF_GLOBAL uint32_t*)(mk + i0) = m;
@@ -1062,11 +1070,60 @@ __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, i
     }
     for (int i = i0; i < min(i0 + 4, n); ++i) {
         const i32x2 st = own[i];
-        const uint32_t m = fb_mask(other, W, x, y, st, eps2);
+        const int32_t e = fb_err(other, W, x, y, st);
         if (fl) fl[i] = (uint32_t)st.x;
         if (co) co[i] = st.y;
-        if (mk) mk[i] = (uint8_t)m;
+        if (mk) mk[i] = e <= eps2 ? 1 : 0;
+        if (er) er[i] = e;
         if (++x == W) { x = 0; ++y; }
+    }
+}
+
+// ----------------------------------------------------- sparsification --
+// Sec. 3.1 (minimum matches s from Table 3): the level-0 image is cut into
+// 3x3 blocks from the origin, partial at the right and bottom borders.  One
+// thread per block counts its consistent matches (error <= eps^2) and, with
+// at least s of them, keeps the lowest error -- a row-major scan with a
+// strict '<' keeps the lowest y*W + x among equals; all nine keep bytes of
+// the block are written.  Lanes take consecutive blocks of a block row, so
+// their reads and writes are contiguous.  grid (ceil(W/3)/256, ceil(H/3), 2 * pairs)
+__global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pairs, int eps2, int s)
+{
+    const PairDev& P = pairs[blockIdx.z >> 1];
+    const int dir = blockIdx.z & 1;
+    uint8_t* keep = P.sparse[dir];
+    if (!keep) return;                                           // output not requested
+    const LevelDev& L = P.lv[0];
+    const int W = L.W, H = L.H;
+    const int x0 = 3 * (blockIdx.x * 256 + threadIdx.x), y0 = 3 * blockIdx.y;
+    if (x0 >= W || y0 >= H) return;
+    const FF_GLOBAL int32_t* err = (const FF_GLOBAL int32_t*)P.fberr[dir];
+    int count = 0, best = -1;
+    int32_t be = 0;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int x = x0 + dx, y = y0 + dy;
+            if (x >= W || y >= H) continue;
+            const int32_t e = err[(uint32_t)y * (uint32_t)W + (uint32_t)x];
+            if (e <= eps2) {
+                ++count;
+                if (best < 0 || e < be) {
+                    be = e;
+                    best = 3 * dy + dx;
+                }
+            }
+        }
+    }
+    if (count < s) best = -1;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int x = x0 + dx, y = y0 + dy;
+            if (x < W && y < H) keep[(size_t)y * W + x] = (3 * dy + dx == best) ? 1 : 0;
+        }
     }
 }
 
@@ -1185,6 +1242,11 @@ void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, i
 void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fb, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
+}
+void launch_sparse(const PairDev* d, int npairs, int eps2, int s, int maxW, int maxH, hipStream_t st)
+{
+    const int nbx = (maxW + 2) / 3, nby = (maxH + 2) / 3;
+    hipLaunchKernelGGL(k_sparse, dim3((nbx + 255) / 256, nby, 2 * npairs), dim3(256), 0, st, d, eps2, s);
 }
 void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, size_t n, hipStream_t st)
 {

@@ -35,6 +35,7 @@ bool launch_line_phase(bool, int, int, int, const PairDev*, int, int, int, int, 
 bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
+void launch_sparse(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
 }  // namespace ff
@@ -163,6 +164,7 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
     pl.nsy = (pl.H[c] + p.seed_stride - 1) / p.seed_stride;
     b += 2 * align_up((size_t)pl.W[c] * pl.H[c] * 64);
     b += 2 * align_up((size_t)pl.nsx * pl.nsy * 8);
+    if (p.flags & FF_SPARSIFY) b += 2 * align_up((size_t)W * H * 4);   // consistency errors
     pl.bytes = b;
     return pl;
 }
@@ -174,7 +176,9 @@ ff_status validate_params(ff_ctx* h, const ff_params& p)
     if (p.iters < 0 || p.iters > 64) return fail(h, FF_ERR_INVALID, "iters must be in 0..64");
     if (p.rs_radius < 0 || p.rs_radius > 1024) return fail(h, FF_ERR_INVALID, "rs_radius must be in 0..1024");
     if (p.fb_eps < 0 || p.fb_eps > 1024) return fail(h, FF_ERR_INVALID, "fb_eps must be in 0..1024");
-    if (p.flags != 0) return fail(h, FF_ERR_INVALID, "flags must be 0");
+    if (p.flags & ~FF_SPARSIFY) return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if ((p.flags & FF_SPARSIFY) && (p.sparse_min < 1 || p.sparse_min > 9))
+        return fail(h, FF_ERR_INVALID, "sparse_min must be in 1..9");
     return FF_OK;
 }
 
@@ -189,8 +193,13 @@ ff_status validate_pair(ff_ctx* h, const ff_pair& q)
     if ((q.width >> (p.levels - 1)) < 1 || (q.height >> (p.levels - 1)) < 1)
         return fail(h, FF_ERR_INVALID, "image too small for the number of levels");
     if (((uintptr_t)q.flow_fwd & 3) || ((uintptr_t)q.flow_bwd & 3) || ((uintptr_t)q.cost_fwd & 3) ||
-        ((uintptr_t)q.cost_bwd & 3))
-        return fail(h, FF_ERR_INVALID, "flow and cost outputs must be 4-byte aligned");
+        ((uintptr_t)q.cost_bwd & 3) || ((uintptr_t)q.fberr_fwd & 3) || ((uintptr_t)q.fberr_bwd & 3))
+        return fail(h, FF_ERR_INVALID, "flow, cost and fberr outputs must be 4-byte aligned");
+    if (p.flags & FF_SPARSIFY) {
+        if (!q.sparse_fwd) return fail(h, FF_ERR_INVALID, "sparse_fwd is required with FF_SPARSIFY");
+    } else if (q.sparse_fwd || q.sparse_bwd) {
+        return fail(h, FF_ERR_INVALID, "sparse outputs need FF_SPARSIFY");
+    }
     return FF_OK;
 }
 
@@ -268,6 +277,17 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
         d.cost[1] = pairs[i].cost_bwd;
         d.mask[0] = pairs[i].mask_fwd;
         d.mask[1] = pairs[i].mask_bwd;
+        d.fberr[0] = pairs[i].fberr_fwd;
+        d.fberr[1] = pairs[i].fberr_bwd;
+        d.sparse[0] = pairs[i].sparse_fwd;
+        d.sparse[1] = pairs[i].sparse_bwd;
+        if (p.flags & FF_SPARSIFY) {
+            const size_t np = (size_t)pl.W[0] * pl.H[0];
+            for (int k = 0; k < 2; ++k) {
+                int32_t* own = (int32_t*)take(np * 4);
+                if (!d.fberr[k]) d.fberr[k] = own;
+            }
+        }
     }
 }
 
@@ -325,8 +345,9 @@ SearchConst search_const(const ff_params& p)
 }
 
 const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn",
-                                    "init", "row_phase", "col_phase", "transpose", "fb"};
-enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_COUNT };
+                                    "init", "row_phase", "col_phase", "transpose", "fb", "sparse"};
+enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_SPARSE,
+       KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
@@ -427,6 +448,8 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     }
     if (stop.active) return fail(h, FF_ERR_INVALID, "debug stage names a point the schedule does not reach");
     FF_TRACED(KN_FB, 0, launch_fb(d, n, sc.eps2, D.maxPx[0], st));
+    if (p.flags & FF_SPARSIFY)
+        FF_TRACED(KN_SPARSE, 0, launch_sparse(d, n, sc.eps2, p.sparse_min, D.maxW[0], D.maxH[0], st));
     return FF_OK;
 }
 

@@ -14,6 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libff.so")
 
 FF_OK, FF_ERR_INVALID, FF_ERR_OOM, FF_ERR_BUDGET, FF_ERR_HIP, FF_ERR_UNSUPPORTED, FF_ERR_BUSY = range(7)
+FF_SPARSIFY = 1                                  # params.flags: 3x3-block sparsification
 STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE = range(5)
 INF = 2**31 - 1
 
@@ -34,7 +35,8 @@ class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("seed_stride", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
                 ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
+                ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("sparse_min", ctypes.c_int32)]
 
 
 class Pair(ctypes.Structure):
@@ -42,7 +44,9 @@ class Pair(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("channels", ctypes.c_int32),
                 ("flow_fwd", ctypes.c_void_p), ("cost_fwd", ctypes.c_void_p),
                 ("mask_fwd", ctypes.c_void_p), ("flow_bwd", ctypes.c_void_p),
-                ("cost_bwd", ctypes.c_void_p), ("mask_bwd", ctypes.c_void_p)]
+                ("cost_bwd", ctypes.c_void_p), ("mask_bwd", ctypes.c_void_p),
+                ("fberr_fwd", ctypes.c_void_p), ("sparse_fwd", ctypes.c_void_p),
+                ("fberr_bwd", ctypes.c_void_p), ("sparse_bwd", ctypes.c_void_p)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -111,11 +115,16 @@ class Matcher:
     [H, W] (gray) or [H, W, 3] (RGB), contiguous."""
 
     def __init__(self, levels=4, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
-                 hbm_budget=0, device=0):
+                 hbm_budget=0, device=0, sparse_min=0):
+        """sparse_min > 0 turns on the 3x3-block sparsification (FF_SPARSIFY)
+        with that minimum number of matches s; outputs then include
+        sparse_f / sparse_b and the consistency errors fberr_f / fberr_b."""
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
-        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget, 0)
+        self.sparse = sparse_min > 0
+        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget,
+                             FF_SPARSIFY if self.sparse else 0, sparse_min)
         h = ctypes.c_void_p()
         st = lib().ff_create(ctypes.byref(self.params), device, ctypes.byref(h))
         if st != FF_OK:
@@ -140,6 +149,10 @@ class Matcher:
             o["mask_b"] = t.empty((H, W), dtype=t.uint8, device=d)
             if cost:
                 o["cost_b"] = t.empty((H, W), dtype=t.int32, device=d)
+        if self.sparse:
+            for sfx in ("f", "b") if bwd else ("f",):
+                o["sparse_" + sfx] = t.empty((H, W), dtype=t.uint8, device=d)
+                o["fberr_" + sfx] = t.empty((H, W), dtype=t.int32, device=d)
         return o
 
     @staticmethod
@@ -157,7 +170,9 @@ class Matcher:
         C = 1 if img1.dim() == 2 else int(img1.shape[2])
         p = Pair(img1.data_ptr(), img2.data_ptr(), W, H, C,
                  self._ptr(out, "flow_f"), self._ptr(out, "cost_f"), self._ptr(out, "mask_f"),
-                 self._ptr(out, "flow_b"), self._ptr(out, "cost_b"), self._ptr(out, "mask_b"))
+                 self._ptr(out, "flow_b"), self._ptr(out, "cost_b"), self._ptr(out, "mask_b"),
+                 self._ptr(out, "fberr_f"), self._ptr(out, "sparse_f"),
+                 self._ptr(out, "fberr_b"), self._ptr(out, "sparse_b"))
         return p
 
     # -- API --------------------------------------------------------------

@@ -68,3 +68,27 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ff, "_lib", None)
     with pytest.raises(ff.FFError):
         ff.lib()
+
+
+def test_struct_layouts_match_the_binding(libff, tmp_path):
+    """The ctypes mirrors of ff_params and ff_pair have the C layout: field
+    offsets and sizes as gcc lays out include/ff.h."""
+    structs = {"ff_params": libff.Params, "ff_pair": libff.Pair}
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "ff.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            src.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src += ["return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
