@@ -193,6 +193,40 @@ def seednn_bench(torch, ff, pair, batch_prof):
     return {"peak_tops": I8_PEAK_TOPS, "grouped_batch": grouped, "large_shape": large}
 
 
+def sparse_bench(torch, ff, pairs, steps):
+    """3x3-block sparsification (Sec. 3.1, s = 7 for KITTI in Table 3) on the
+    benchmark batch: whole-step throughput with it on, and the selection
+    kernel against HBM.  Algorithmic bytes per level-0 pixel and direction:
+    4 (consistency error read) + 1 (keep byte written); the error plane the
+    consistency kernel writes with it (4 B) is charged to that kernel."""
+    W, H = W0, H0
+    m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, sparse_min=7)
+    m.set_tuning(SCHEDULE_C1)
+    outs = [m._outputs(H, W, True, True) for _ in pairs]
+    for _ in range(2):
+        m.match_batch(pairs, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.match_batch(pairs, outs=outs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.profile(True)
+    for _ in range(steps):
+        m.match_batch(pairs, outs=outs)
+    prof = m.profile_read()
+    m.profile(False)
+    kept = float(sum(o["sparse_f"].float().mean().item() for o in outs[:8]) / 8)
+    m.close()
+    n, ms = prof["sparse"]
+    avg_s = ms / n / 1000.0
+    bytes_launch = 5 * W * H * 2 * len(pairs)
+    gbs = bytes_launch / avg_s / 1e9
+    return {"s": 7, "pairs_per_s": len(pairs) * steps / wall, "kept_fraction_fwd": kept,
+            "kernel": {"name": "sparse", "avg_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+                       "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}}
+
+
 def c4_bench(torch, ff, n_pairs):
     """Config 4: n uneven gray pairs (sides 96..256, translations up to
     +-24 px, 3 levels) as ONE batched call (replayed hipGraph, tuned schedule)
@@ -351,6 +385,9 @@ def main():
         dtp = time.perf_counter() - t0
         plain = {"pairs_per_s": args.batch * max(1, args.steps // 4) / dtp}
 
+    print("[bench] sparsification leg", file=sys.stderr, flush=True)
+    sparse = sparse_bench(torch, ff, pairs, max(2, args.steps // 4))
+
     serving = None
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_requests} mixed requests, served vs plain", file=sys.stderr, flush=True)
@@ -395,6 +432,7 @@ def main():
         "kernels": kernels,
         "plain": plain,
         "seed_nn": seednn,
+        "sparsify": sparse,
         "serving": serving,
         "batch_c4": batch_c4,
         "cpu_baseline": cpu,
