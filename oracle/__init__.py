@@ -35,7 +35,10 @@ def build(force: bool = True) -> str:
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("seed_stride", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
-                ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("cost_kind", ctypes.c_int32)]
+
+
+COST_WH, COST_CENSUS = 0, 1
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -60,6 +63,11 @@ def lib():
         l.ffo_nearest.argtypes = [P, P, i]
         l.ffo_fb_error.argtypes = [i, i, P, P, P, P, P]
         l.ffo_sparsify.argtypes = [i, i, P, P, i, P]
+        l.ffo_census.argtypes = [P, i, i, P]
+        l.ffo_cost_census.argtypes = [P, P, i, i, i, i, i, i]
+        l.ffo_cost_census.restype = ctypes.c_int32
+        l.ffo_sweep_census.argtypes = [P, P, i, i, i, P, P]
+        l.ffo_random_search_census.argtypes = [P, P, i, i, i, i, i, i, ctypes.c_uint64, P, P]
         l.ffo_nearest.restype = ctypes.c_int32
         l.ffo_philox4x32_10.argtypes = [P, P, P]
         l.ffo_cost.argtypes = [P, P, i, i, i, i, i, i]
@@ -77,8 +85,8 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED) -> Params:
-    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed)
+def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, cost_kind=COST_WH) -> Params:
+    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind)
 
 
 def gray(img: np.ndarray) -> np.ndarray:
@@ -165,6 +173,43 @@ def random_search(DA, DB, flow, cst, level, it, pss, radius, seed):
     c = np.array(cst, dtype=np.int32, copy=True, order="C")
     lib().ffo_random_search(_p(DA), _p(DB), W, H, level, it, pss, radius,
                             ctypes.c_uint64(seed), _p(f), _p(c))
+    return f, c
+
+
+def census(plane: np.ndarray) -> np.ndarray:
+    """Sec. 3.1 7x7 Census strings of a luma plane, [H, W] uint64."""
+    plane = np.ascontiguousarray(plane, dtype=np.uint8)
+    H, W = plane.shape
+    out = np.empty((H, W), np.uint64)
+    lib().ffo_census(_p(plane), W, H, _p(out))
+    return out
+
+
+def cost_census(CA, CB, x, y, fx, fy) -> int:
+    CA = np.ascontiguousarray(CA, dtype=np.uint64)
+    CB = np.ascontiguousarray(CB, dtype=np.uint64)
+    H, W = CA.shape
+    return int(lib().ffo_cost_census(_p(CA), _p(CB), W, H, x, y, fx, fy))
+
+
+def sweep_census(CA, CB, flow, cst, dir_code: int):
+    CA = np.ascontiguousarray(CA, dtype=np.uint64)
+    CB = np.ascontiguousarray(CB, dtype=np.uint64)
+    H, W = CA.shape
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_sweep_census(_p(CA), _p(CB), W, H, dir_code, _p(f), _p(c))
+    return f, c
+
+
+def random_search_census(CA, CB, flow, cst, level, it, pss, radius, seed):
+    CA = np.ascontiguousarray(CA, dtype=np.uint64)
+    CB = np.ascontiguousarray(CB, dtype=np.uint64)
+    H, W = CA.shape
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_random_search_census(_p(CA), _p(CB), W, H, level, it, pss, radius,
+                                   ctypes.c_uint64(seed), _p(f), _p(c))
     return f, c
 
 

@@ -117,6 +117,57 @@ int32_t ffo_cost(const int8_t* DA, const int8_t* DB, int W, int H, int x, int y,
     return s;
 }
 
+/* ------------------------------------------------------------- Census --- */
+/* The alternative matching cost of Sec. 3.1: the Hamming distance of the
+ * binary patterns of the Census transform over a 7x7 patch (Zabih and
+ * Woodfill).  Reading: on the luma plane (as every other step here), patch
+ * centred on the pixel, border replicated, bit set when the neighbour is
+ * strictly darker than the centre, neighbours in row-major order.          */
+void ffo_census(const uint8_t* P, int W, int H, uint64_t* out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int c = P[(size_t)y * W + x];
+            uint64_t bits = 0;
+            int k = 0;
+            for (int dy = -3; dy <= 3; ++dy)
+                for (int dx = -3; dx <= 3; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    int v = P[(size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+                    if (v < c) bits |= (uint64_t)1 << k;
+                    ++k;
+                }
+            out[(size_t)y * W + x] = bits;
+        }
+}
+
+int32_t ffo_cost_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int x, int y, int fx, int fy)
+{
+    int qx = x + fx, qy = y + fy;
+    if (qx < 0 || qx >= W || qy < 0 || qy >= H) return FFO_INF;
+    uint64_t d = CA[(size_t)y * W + x] ^ CB[(size_t)qy * W + qx];
+    int32_t n = 0;
+    while (d) {
+        n += (int32_t)(d & 1u);
+        d >>= 1;
+    }
+    return n;
+}
+
+/* A level's matching-cost plane of one image: the descriptors (SAD) or the
+ * Census strings (Hamming), as params.cost_kind selects.                    */
+typedef struct {
+    int kind;
+    const int8_t* desc;
+    const uint64_t* cen;
+} cplane;
+
+static int32_t plane_cost(const cplane* A, const cplane* B, int W, int H, int x, int y, int fx, int fy)
+{
+    if (A->kind == FFO_COST_CENSUS) return ffo_cost_census(A->cen, B->cen, W, H, x, y, fx, fy);
+    return ffo_cost(A->desc, B->desc, W, H, x, y, fx, fy);
+}
+
 /* ------------------------------------------------------------ seed NN --- */
 /* Initial matches at the lowest resolution (Sec. 3.1).  The paper matches
  * the Walsh-Hadamard descriptors with kd-trees; the reading here is the
@@ -191,8 +242,8 @@ void ffo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * each pixel compares its own flow with the flow its predecessor on the
  * line holds after that predecessor was visited, and takes the
  * predecessor's flow only if its cost is strictly lower.                   */
-void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
-               int16_t* flow, int32_t* cost)
+static void sweep_planes(const cplane* A, const cplane* B, int W, int H, int dir_code,
+                         int16_t* flow, int32_t* cost)
 {
     int horizontal = (dir_code == 0 || dir_code == 1);
     int lines = horizontal ? H : W;
@@ -206,7 +257,7 @@ void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
             else                    { x = line; y = len - 1 - s; px = x; py = y + 1; }
             size_t p = (size_t)y * W + x, q = (size_t)py * W + px;
             int gx = flow[2 * q], gy = flow[2 * q + 1];
-            int32_t e = ffo_cost(DA, DB, W, H, x, y, gx, gy);
+            int32_t e = plane_cost(A, B, W, H, x, y, gx, gy);
             if (e < cost[p]) {
                 flow[2 * p] = (int16_t)gx;
                 flow[2 * p + 1] = (int16_t)gy;
@@ -214,6 +265,20 @@ void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
             }
         }
     }
+}
+
+void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
+               int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_WH, DA, NULL}, B = {FFO_COST_WH, DB, NULL};
+    sweep_planes(&A, &B, W, H, dir_code, flow, cost);
+}
+
+void ffo_sweep_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int dir_code,
+                      int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_CENSUS, NULL, CA}, B = {FFO_COST_CENSUS, NULL, CB};
+    sweep_planes(&A, &B, W, H, dir_code, flow, cost);
 }
 
 /* ------------------------------------------------------- random search -- */
@@ -226,9 +291,9 @@ void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
  * counter is (y*W + x, level, (iter << 2) | pass, j >> 1) and the key is
  * the 64-bit seed split into (low, high) words; trial j uses words (0, 1)
  * when j is even and (2, 3) when j is odd.                                 */
-void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int level,
-                       int iter, int pass, int radius, uint64_t seed,
-                       int16_t* flow, int32_t* cost)
+static void random_search_planes(const cplane* A, const cplane* B, int W, int H, int level,
+                                 int iter, int pass, int radius, uint64_t seed,
+                                 int16_t* flow, int32_t* cost)
 {
     int J = 0;
     while ((radius >> J) > 0) ++J;                 /* floor(log2 R) + 1 */
@@ -254,7 +319,7 @@ void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int lev
                 int dy = (int)(uy % span) - r;
                 int cx = v0x + dx, cy = v0y + dy;
                 if (cx == bx && cy == by) continue;
-                int32_t c = ffo_cost(DA, DB, W, H, x, y, cx, cy);
+                int32_t c = plane_cost(A, B, W, H, x, y, cx, cy);
                 if (c < bc) { bx = cx; by = cy; bc = c; }
             }
             flow[2 * p] = (int16_t)bx;
@@ -263,11 +328,28 @@ void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int lev
         }
 }
 
+void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int level,
+                       int iter, int pass, int radius, uint64_t seed,
+                       int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_WH, DA, NULL}, B = {FFO_COST_WH, DB, NULL};
+    random_search_planes(&A, &B, W, H, level, iter, pass, radius, seed, flow, cost);
+}
+
+void ffo_random_search_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int level,
+                              int iter, int pass, int radius, uint64_t seed,
+                              int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_CENSUS, NULL, CA}, B = {FFO_COST_CENSUS, NULL, CB};
+    random_search_planes(&A, &B, W, H, level, iter, pass, radius, seed, flow, cost);
+}
+
 /* --------------------------------------------------------- full search -- */
 typedef struct {
     int W, H;
     uint8_t* pyr[2];       /* gray level of image 1 and image 2 */
     int8_t* desc[2];       /* descriptors of image 1 and image 2 */
+    uint64_t* cen[2];      /* Census strings (cost_kind = FFO_COST_CENSUS)  */
 } level_t;
 
 static void trace_call(ffo_trace_fn trace, void* user, int dir, int level, int iter, int stage,
@@ -289,6 +371,8 @@ static void search_direction(const ffo_params* p, const level_t* lv, int ia, int
         int W = lv[l].W, H = lv[l].H;
         const int8_t* DA = lv[l].desc[ia];
         const int8_t* DB = lv[l].desc[ib];
+        /* seeds always match descriptors; every other cost uses the plane  */
+        const cplane A = {p->cost_kind, DA, lv[l].cen[ia]}, B = {p->cost_kind, DB, lv[l].cen[ib]};
         int16_t* nflow = (l == 0) ? flow0 : (int16_t*)malloc(sizeof(int16_t) * 2 * (size_t)W * H);
         int32_t* ncost = (l == 0) ? cost0 : (int32_t*)malloc(sizeof(int32_t) * (size_t)W * H);
         if (l == L - 1) {
@@ -306,7 +390,7 @@ static void search_direction(const ffo_params* p, const level_t* lv, int ia, int
                     size_t pp = (size_t)y * W + x;
                     nflow[2 * pp] = (int16_t)fx;
                     nflow[2 * pp + 1] = (int16_t)fy;
-                    ncost[pp] = ffo_cost(DA, DB, W, H, x, y, fx, fy);
+                    ncost[pp] = plane_cost(&A, &B, W, H, x, y, fx, fy);
                 }
             free(idx);
         } else {
@@ -319,7 +403,7 @@ static void search_direction(const ffo_params* p, const level_t* lv, int ia, int
                     int fx = 2 * flow[2 * cp], fy = 2 * flow[2 * cp + 1];
                     nflow[2 * pp] = (int16_t)fx;
                     nflow[2 * pp + 1] = (int16_t)fy;
-                    ncost[pp] = ffo_cost(DA, DB, W, H, x, y, fx, fy);
+                    ncost[pp] = plane_cost(&A, &B, W, H, x, y, fx, fy);
                 }
             free(flow);
             free(cost);
@@ -330,19 +414,19 @@ static void search_direction(const ffo_params* p, const level_t* lv, int ia, int
         ph = H;
         trace_call(trace, user, dir, l, -1, 0, W, H, flow, cost);
         for (int t = 0; t < p->iters; ++t) {
-            ffo_sweep(DA, DB, W, H, 0, flow, cost);
+            sweep_planes(&A, &B, W, H, 0, flow, cost);
             trace_call(trace, user, dir, l, t, 1, W, H, flow, cost);
-            ffo_sweep(DA, DB, W, H, 1, flow, cost);
+            sweep_planes(&A, &B, W, H, 1, flow, cost);
             trace_call(trace, user, dir, l, t, 2, W, H, flow, cost);
-            ffo_random_search(DA, DB, W, H, l, t, 0, p->rs_radius, p->seed, flow, cost);
+            random_search_planes(&A, &B, W, H, l, t, 0, p->rs_radius, p->seed, flow, cost);
             trace_call(trace, user, dir, l, t, 3, W, H, flow, cost);
-            ffo_sweep(DA, DB, W, H, 2, flow, cost);
+            sweep_planes(&A, &B, W, H, 2, flow, cost);
             trace_call(trace, user, dir, l, t, 4, W, H, flow, cost);
-            ffo_random_search(DA, DB, W, H, l, t, 1, p->rs_radius, p->seed, flow, cost);
+            random_search_planes(&A, &B, W, H, l, t, 1, p->rs_radius, p->seed, flow, cost);
             trace_call(trace, user, dir, l, t, 5, W, H, flow, cost);
-            ffo_sweep(DA, DB, W, H, 3, flow, cost);
+            sweep_planes(&A, &B, W, H, 3, flow, cost);
             trace_call(trace, user, dir, l, t, 6, W, H, flow, cost);
-            ffo_random_search(DA, DB, W, H, l, t, 2, p->rs_radius, p->seed, flow, cost);
+            random_search_planes(&A, &B, W, H, l, t, 2, p->rs_radius, p->seed, flow, cost);
             trace_call(trace, user, dir, l, t, 7, W, H, flow, cost);
         }
     }
@@ -425,7 +509,7 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
     if (!p || !img1 || !img2 || !flow_f || !mask_f) return -1;
     if (C != 1 && C != 3) return -1;
     if (p->levels < 1 || p->levels > 16 || p->seed_stride < 1 || p->iters < 0 ||
-        p->rs_radius < 0 || p->fb_eps < 0)
+        p->rs_radius < 0 || p->fb_eps < 0 || (p->cost_kind != FFO_COST_WH && p->cost_kind != FFO_COST_CENSUS))
         return -1;
     if (W < 1 || H < 1 || (W >> (p->levels - 1)) < 1 || (H >> (p->levels - 1)) < 1) return -1;
 
@@ -446,6 +530,10 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
         for (int l = 0; l < L; ++l) {
             lv[l].desc[i] = (int8_t*)malloc((size_t)lv[l].W * lv[l].H * FFO_K);
             ffo_descriptors(lv[l].pyr[i], lv[l].W, lv[l].H, lv[l].desc[i]);
+            if (p->cost_kind == FFO_COST_CENSUS) {
+                lv[l].cen[i] = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)lv[l].W * lv[l].H);
+                ffo_census(lv[l].pyr[i], lv[l].W, lv[l].H, lv[l].cen[i]);
+            }
         }
     }
 
@@ -467,6 +555,7 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
         for (int i = 0; i < 2; ++i) {
             free(lv[l].pyr[i]);
             free(lv[l].desc[i]);
+            free(lv[l].cen[i]);
         }
     free(lv);
     return 0;

@@ -30,7 +30,11 @@ typedef struct {
     int32_t  rs_radius;     /* random-search radius R (16): R, R>>1, ..., 1   */
     int32_t  fb_eps;        /* consistency threshold epsilon in px (1)       */
     uint64_t seed;          /* random-search key                             */
+    int32_t  cost_kind;     /* FFO_COST_WH (0) or FFO_COST_CENSUS (1)         */
 } ffo_params;
+
+#define FFO_COST_WH     0   /* SAD of the 16 Walsh-Hadamard coefficients     */
+#define FFO_COST_CENSUS 1   /* Hamming distance of 7x7 Census bit strings    */
 
 /* Trace hook: called after every stage with the direction's state.
  * stage: 0 = level init, 1 = LR, 2 = RL, 3 = RS0, 4 = TB, 5 = RS1, 6 = BT,
@@ -52,6 +56,13 @@ void ffo_seed_nn(const int8_t* DA, const int8_t* DB, int W, int H, int stride, i
  * DB: index of the first minimum of the squared L2 distance.  Lets a test
  * check single seeds of a plane too large to search whole.               */
 int32_t ffo_nearest(const int8_t* a, const int8_t* DB, int N);
+/* 7x7 Census transform (Sec. 3.1; Zabih and Woodfill): bit k, for the k-th
+ * of the 48 neighbours (dx, dy) in [-3, 3]^2 other than the centre taken in
+ * row-major order (dy outer, dx inner), is 1 when the neighbour is strictly
+ * darker than the centre; border replicated.  out is [H][W].              */
+void ffo_census(const uint8_t* P, int W, int H, uint64_t* out);
+/* Census matching cost: Hamming distance (0..48), INF outside image B.   */
+int32_t ffo_cost_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int x, int y, int fx, int fy);
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11).                        */
 void ffo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Matching cost: SAD of the two descriptors, INF when p+f leaves image B.  */
@@ -64,6 +75,12 @@ void ffo_sweep(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code,
 void ffo_random_search(const int8_t* DA, const int8_t* DB, int W, int H, int level,
                        int iter, int pass, int radius, uint64_t seed,
                        int16_t* flow, int32_t* cost);
+/* The same two steps with the Census cost (planes from ffo_census).       */
+void ffo_sweep_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int dir_code,
+                      int16_t* flow, int32_t* cost);
+void ffo_random_search_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int level,
+                              int iter, int pass, int radius, uint64_t seed,
+                              int16_t* flow, int32_t* cost);
 
 /* Full search for one pair.  img1/img2 are [H][W][C] uint8, C in {1, 3}.
  * flow_* [H][W][2] int16, cost_* [H][W] int32, mask_* [H][W] uint8.

@@ -650,3 +650,131 @@ def test_schedule_order_is_lr_rl_rs_tb_rs_bt_rs(orc):
                 cur = st[(0, l, t, s)]
                 assert np.array_equal(nxt[0], cur[0]) and np.array_equal(nxt[1], cur[1]), (l, t, s)
                 prev = cur
+
+
+# ------------------------------------------------------------ Census cost --
+def _census_by_shifts(P):
+    """Census strings from whole shifted planes (edge-padded numpy views):
+    bit k is set where the k-th neighbour (row-major over the 7x7 window,
+    centre skipped) is strictly darker than the centre."""
+    H, W = P.shape
+    pad = np.pad(P.astype(np.int32), 3, mode="edge")
+    centre = P.astype(np.int32)
+    out = np.zeros((H, W), np.uint64)
+    k = 0
+    for dy in range(-3, 4):
+        for dx in range(-3, 4):
+            if dx == 0 and dy == 0:
+                continue
+            nb = pad[3 + dy:3 + dy + H, 3 + dx:3 + dx + W]
+            out |= (nb < centre).astype(np.uint64) << np.uint64(k)
+            k += 1
+    assert k == 48
+    return out
+
+
+def test_census_matches_shifted_plane_formulation(orc):
+    rng = np.random.default_rng(14)
+    for (H, W) in [(1, 1), (3, 5), (7, 7), (20, 17), (9, 40)]:
+        for levels in (2, 256):                   # many ties, then few
+            P = rng.integers(0, levels, size=(H, W)).astype(np.uint8)
+            assert np.array_equal(orc.census(P), _census_by_shifts(P)), (H, W, levels)
+
+
+def test_census_special_cases(orc):
+    assert not orc.census(np.full((9, 9), 77, np.uint8)).any()            # flat: nothing darker
+    P = np.zeros((11, 11), np.uint8)
+    P[5, 5] = 200
+    C = orc.census(P)
+    assert int(C[5, 5]) == (1 << 48) - 1                                   # every neighbour darker
+    assert int(C[5, 6]) == 0 and int(C[0, 0]) == 0                         # the bright pixel is never darker
+    ramp = np.tile(np.arange(0, 160, 10, dtype=np.uint8), (9, 1))         # increases with x
+    C = orc.census(ramp)
+    bits = [int(v) for v in np.unpackbits(C[4, 8:9].view(np.uint8), bitorder="little")[:48]]
+    # darker neighbours are exactly those to the left: dx = -3..-1 in each of the 7 rows
+    expect = []
+    for dy in range(-3, 4):
+        for dx in range(-3, 4):
+            if (dx, dy) != (0, 0):
+                expect.append(1 if dx < 0 else 0)
+    assert bits == expect
+
+
+def test_census_cost_is_hamming_distance(orc):
+    rng = np.random.default_rng(15)
+    P1 = rng.integers(0, 256, size=(12, 10)).astype(np.uint8)
+    P2 = rng.integers(0, 256, size=(12, 10)).astype(np.uint8)
+    CA, CB = orc.census(P1), orc.census(P2)
+    for _ in range(200):
+        x, y = int(rng.integers(0, 10)), int(rng.integers(0, 12))
+        fx, fy = int(rng.integers(-12, 13)), int(rng.integers(-14, 15))
+        c = orc.cost_census(CA, CB, x, y, fx, fy)
+        qx, qy = x + fx, y + fy
+        if not (0 <= qx < 10 and 0 <= qy < 12):
+            assert c == orc.INF
+            continue
+        d = np.array([CA[y, x] ^ CB[qy, qx]], np.uint64).view(np.uint8)
+        assert c == int(np.unpackbits(d).sum()) and 0 <= c <= 48
+        assert c == orc.cost_census(CB, CA, qx, qy, -fx, -fy)
+
+
+@pytest.fixture(scope="module")
+def census_problem(orc):
+    rng = np.random.default_rng(16)
+    i1, i2, _ = synth.translated_pair(rng, 40, 24, d=(3, -2), rect=(10, 8), rect_d=(-4, 3))
+    CA, CB = orc.census(orc.gray(i1)), orc.census(orc.gray(i2))
+    f0 = rng.integers(-4, 5, size=(24, 40, 2)).astype(np.int16)
+    c0 = np.array([[orc.cost_census(CA, CB, x, y, int(f0[y, x, 0]), int(f0[y, x, 1])) for x in range(40)]
+                   for y in range(24)], np.int32)
+    return CA, CB, f0, c0
+
+
+@pytest.mark.parametrize("dir_code", [0, 1, 2, 3])
+def test_census_sweep_is_the_scanline_fixed_point(orc, census_problem, dir_code):
+    CA, CB, f0, c0 = census_problem
+    f1, c1 = orc.sweep_census(CA, CB, f0, c0, dir_code)
+    H, W = CA.shape
+    for y in range(H):
+        for x in range(W):
+            pred = {0: (x - 1, y), 1: (x + 1, y), 2: (x, y - 1), 3: (x, y + 1)}[dir_code]
+            if not (0 <= pred[0] < W and 0 <= pred[1] < H):
+                assert tuple(f1[y, x]) == tuple(f0[y, x]) and c1[y, x] == c0[y, x]
+                continue
+            g = f1[pred[1], pred[0]]
+            e = orc.cost_census(CA, CB, x, y, int(g[0]), int(g[1]))
+            if e < c0[y, x]:
+                assert tuple(f1[y, x]) == tuple(g) and c1[y, x] == e
+            else:
+                assert tuple(f1[y, x]) == tuple(f0[y, x]) and c1[y, x] == c0[y, x]
+    assert np.any(c1 < c0)
+
+
+def test_census_random_search_invariants(orc, census_problem):
+    CA, CB, f0, c0 = census_problem
+    H, W = CA.shape
+    f1, c1 = orc.random_search_census(CA, CB, f0, c0, 1, 0, 2, 8, 0xC0FFEE)
+    assert np.all(c1 <= c0) and np.any(c1 < c0)
+    assert np.all(np.abs(f1.astype(np.int32) - f0.astype(np.int32)).max(axis=-1) <= 8)
+    for y in range(H):
+        for x in range(W):
+            assert c1[y, x] == orc.cost_census(CA, CB, x, y, int(f1[y, x, 0]), int(f1[y, x, 1]))
+
+
+def test_census_end_to_end(orc):
+    rng = np.random.default_rng(17)
+    img = synth._to_u8(synth.noise_texture(rng, 64, 96))
+    r = orc.match(img, img, _prm(orc, cost_kind=orc.COST_CENSUS))
+    assert np.all(r["flow_f"] == 0) and np.all(r["cost_f"] == 0) and np.all(r["mask_f"] == 1)
+    i1, i2, _ = synth.translated_pair(np.random.default_rng(18), 128, 96, d=(8, -4), rect=(0, 0), noise_sd=0.0)
+    r = orc.match(i1, i2, _prm(orc, cost_kind=orc.COST_CENSUS))
+    m = 4 + 8
+    inner = r["flow_f"][m:96 - m, m:128 - m]
+    assert np.all(inner[..., 0] == 8) and np.all(inner[..., 1] == -4)
+    assert np.all(r["cost_f"][m:96 - m, m:128 - m] == 0)
+    i1, i2, _ = synth.config0()
+    a = orc.match(i1, i2, _prm(orc, cost_kind=orc.COST_CENSUS))
+    b = orc.match(i2, i1, _prm(orc, cost_kind=orc.COST_CENSUS))
+    assert np.array_equal(a["flow_b"], b["flow_f"]) and np.array_equal(a["cost_b"], b["cost_f"])
+    assert a["cost_f"][a["cost_f"] != orc.INF].max() <= 48
+    w = orc.match(i1, i2, _prm(orc))
+    assert not np.array_equal(w["cost_f"], a["cost_f"])        # the cost kind is honoured
