@@ -12,7 +12,11 @@
  *   - descriptors: the 16 lowest-sequency 2-D Walsh-Hadamard coefficients of
  *     the 8x8 patch (offsets -3..+4, replicated border), floor(c / 64), DC
  *     shifted by -128, as int8;
- *   - cost: SAD of two descriptors; INT32_MAX when the target leaves image B;
+ *   - cost: SAD of two descriptors, or (FF_COST_CENSUS) the Hamming distance
+ *     of two 7x7 Census strings of the luma -- bit k for the k-th of the 48
+ *     neighbours in row-major order, set when the neighbour is strictly
+ *     darker than the centre, border replicated; INT32_MAX when the target
+ *     leaves image B;
  *   - seeds: exact nearest neighbour (squared L2, lowest linear index on
  *     ties) of every stride-grid pixel at the coarsest level among all pixels;
  *   - per level: init (seed of the pixel's stride cell, or twice the parent
@@ -59,6 +63,9 @@ typedef enum {
 
 /* flags */
 #define FF_SPARSIFY 1u      /* compute sparse_fwd / sparse_bwd (3x3-block selection) */
+#define FF_COST_CENSUS 2u   /* matching cost = Hamming distance of 7x7 Census strings
+                               (Sec. 3.1) instead of descriptor SAD; seeds still
+                               match descriptors; staged schedules unsupported     */
 
 /* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 and s = 7 for
  * KITTI, epsilon = 7 and s = 4 for MPI Sintel). */
@@ -70,7 +77,7 @@ typedef struct {
     int32_t  fb_eps;        /* consistency threshold in px, 0..1024 (1)          */
     uint64_t seed;          /* random-search key                                 */
     uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
-    uint32_t flags;         /* 0 or FF_SPARSIFY                                  */
+    uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS, or 0                */
     int32_t  sparse_min;    /* s: matches a 3x3 block needs to keep one, 1..9
                                (7); read only with FF_SPARSIFY                 */
 } ff_params;
@@ -192,15 +199,17 @@ typedef enum {
     FF_STAGE_PYRAMID = 1,   /* image `image` level `level`: [H_l][W_l] uint8          */
     FF_STAGE_DESC = 2,      /* image `image` level `level`: [H_l][W_l][16] int8       */
     FF_STAGE_SEEDS = 3,     /* direction `dir`: seed-grid NN index, [nsy][nsx] int32  */
-    FF_STAGE_STATE = 4      /* direction `dir`, level, iter, step: [H_l][W_l] of
+    FF_STAGE_STATE = 4,     /* direction `dir`, level, iter, step: [H_l][W_l] of
                                {int16 dx, int16 dy, int32 cost}; step 0 = after init
                                (iter ignored), 1 LR, 2 RL, 3 RS0, 4 TB, 5 RS1, 6 BT,
                                7 RS2                                                 */
+    FF_STAGE_CENSUS = 5     /* image `image` level `level`: [H_l][W_l] uint64 Census
+                               strings (handles created with FF_COST_CENSUS)         */
 } ff_stage_kind;
 
 typedef struct {
     int32_t kind;           /* ff_stage_kind                     */
-    int32_t image;          /* 0 = img1, 1 = img2 (GRAY/PYRAMID/DESC) */
+    int32_t image;          /* 0 = img1, 1 = img2 (GRAY/PYRAMID/DESC/CENSUS) */
     int32_t dir;            /* 0 = forward, 1 = backward (SEEDS/STATE) */
     int32_t level;
     int32_t iter;

@@ -31,6 +31,8 @@ struct LevelDev {
     uint8_t* descT[2];
     int2* state[2];
     int2* stateT[2];
+    uint8_t* cen[2];                 // 7x7 Census strings, u64 per pixel (Census cost only)
+    uint8_t* cenT[2];                // column-major copy
 };
 
 struct PairDev {

@@ -32,6 +32,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef FF_GLOBAL const uint8_t gcu8;
 typedef FF_GLOBAL const u32x4 gcu4;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef FF_GLOBAL const u32x2 gcu2;
 typedef FF_GLOBAL i32x2 gi2;
 typedef __attribute__((address_space(3))) i32x2 li2;
 
@@ -73,6 +75,39 @@ __device__ __forceinline__ int32_t cost_at(gcu8* __restrict__ DB, int W, int H, 
 __device__ __forceinline__ uint4 load_desc(gcu8* __restrict__ D, size_t idx)
 {
     return ld16(D + idx * 16);
+}
+
+// The two matching features of Sec. 3.1 the search can run on: the 16
+// Walsh-Hadamard coefficients (biased bytes; cost = SAD, four v_sad_u8) or
+// the 48-bit 7x7 Census string (cost = Hamming distance, two v_bcnt).
+template <int CK> struct Feat;
+template <> struct Feat<0> {
+    using T = uint4;
+    __device__ static T load(gcu8* __restrict__ base, size_t idx) { return ld16(base + idx * 16); }
+    __device__ static T zero() { return make_uint4(0, 0, 0, 0); }
+    __device__ static int32_t dist(T a, T b) { return sad16(a, b); }
+};
+template <> struct Feat<1> {
+    using T = uint2;
+    __device__ static T load(gcu8* __restrict__ base, size_t idx)
+    {
+        const u32x2 v = *(gcu2*)(base + idx * 8);
+        return make_uint2(v.x, v.y);
+    }
+    __device__ static T zero() { return make_uint2(0, 0); }
+    __device__ static int32_t dist(T a, T b) { return (int32_t)(__popc(a.x ^ b.x) + __popc(a.y ^ b.y)); }
+};
+
+// Matching cost of pixel (x, y) of A, feature a, under flow f against the
+// feature plane DB of B (layout by COL); INF when the target leaves the
+// image, and then no load is issued.
+template <bool COL, int CK>
+__device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f,
+                                             typename Feat<CK>::T a)
+{
+    const int qx = x + flow_x(f), qy = y + flow_y(f);
+    if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
+    return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)));
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4-word S-P network,
@@ -331,6 +366,103 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
     }
 }
 
+// ------------------------------------------------------------- Census ---
+// 7x7 Census strings (Sec. 3.1, the Census matching cost): bit k, for the
+// k-th of the 48 neighbours (dx, dy) in [-3, 3]^2 other than the centre in
+// row-major order, is set when the neighbour is strictly darker than the
+// centre; border replicated.  A block covers 64 x 32 outputs with its
+// 70 x 38 input window in LDS (all byte loads in flight before the first
+// LDS write); thread (c, g) builds column c, rows 8g .. 8g+7.  Stored as
+// u64 row-major from registers and column-major through LDS, 16 rows at a
+// time, both coalesced.  grid (ceil(W/64), ceil(H/32), 2 * pairs).
+constexpr int kCenTX = 64, kCenTY = 32;
+
+__global__ __launch_bounds__(256) void k_census(const PairDev* __restrict__ pairs, int level)
+{
+    const PairDev& P = pairs[blockIdx.z >> 1];
+    const int img = blockIdx.z & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, H = L.H;
+    const int x0 = blockIdx.x * kCenTX, y0 = blockIdx.y * kCenTY;
+    if (x0 >= W || y0 >= H) return;
+    constexpr int TR = kCenTY + 6, TC = kCenTX + 6;
+    __shared__ union {
+        uint8_t tile[TR][kCenTX + 8];
+        uint2 res[kCenTY / 2][kCenTX + 1];
+    } sm;
+    gcu8* __restrict__ src = (gcu8*)L.gray[img];
+    constexpr int NT = TR * TC, NI = (NT + 255) / 256;
+    uint8_t v[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int r = i / TC, c = i % TC;
+        const int gy = min(max(y0 - 3 + r, 0), H - 1);
+        const int gx = min(max(x0 - 3 + c, 0), W - 1);
+        v[k] = i < NT ? src[(uint32_t)gy * (uint32_t)W + (uint32_t)gx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NT) sm.tile[i / TC][i % TC] = v[k];
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    uint32_t rows[14][2];                                        // window rows 8g .. 8g+13, bytes c .. c+7
+#pragma unroll
+    for (int r = 0; r < 14; ++r) {
+        const uint8_t* t = &sm.tile[8 * g + r][c];
+        rows[r][0] = (uint32_t)t[0] | ((uint32_t)t[1] << 8) | ((uint32_t)t[2] << 16) | ((uint32_t)t[3] << 24);
+        rows[r][1] = (uint32_t)t[4] | ((uint32_t)t[5] << 8) | ((uint32_t)t[6] << 16);
+    }
+    uint2 out[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t centre = (rows[i + 3][0] >> 24) & 0xFFu;       // byte 3 of row i+3
+        uint32_t lo = 0, hi = 0;
+        int k = 0;
+#pragma unroll
+        for (int dy = 0; dy < 7; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 7; ++dx) {
+                if (dy == 3 && dx == 3) continue;
+                const uint32_t nb = (rows[i + dy][dx >> 2] >> (8 * (dx & 3))) & 0xFFu;
+                const uint32_t bit = nb < centre ? 1u : 0u;
+                if (k < 32) lo |= bit << k;
+                else hi |= bit << (k - 32);
+                ++k;
+            }
+        }
+        out[i] = make_uint2(lo, hi);
+    }
+    const int x = x0 + c;
+    FF_GLOBAL u32x2* dst = (FF_GLOBAL u32x2*)L.cen[img];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
+        const int y = y0 + 8 * g + i;
+        if (x < W && y < H) dst[(uint32_t)y * (uint32_t)W + (uint32_t)x] = u32x2{out[i].x, out[i].y};
+    }
+    FF_GLOBAL u32x2* dstT = (FF_GLOBAL u32x2*)L.cenT[img];
+    for (int half = 0; half < 2; ++half) {                       // column-major, 16 rows at a time
+        __syncthreads();
+        if ((g >> 1) == half) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sm.res[8 * (g & 1) + i][c] = out[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {                            // lanes along y
+            const int i = threadIdx.x + 256 * k;
+            const int r = i % 16, cc = i / 16;
+            const int xx = x0 + cc, yy = y0 + 16 * half + r;
+            if (xx < W && yy < H) {
+                const uint2 w = sm.res[r][cc];
+                dstT[(uint32_t)xx * (uint32_t)H + (uint32_t)yy] = u32x2{w.x, w.y};
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ seed NN ---
 // Database records for the exact seed search at the coarsest level.  The
 // score 2 a.b - |b|^2 (maximised; equivalent to minimising |a - b|^2) is one
@@ -509,9 +641,10 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 // ----------------------------------------------------------- level init --
 // Coarsest level: every pixel takes the flow of the seed of its stride cell.
 // Finer levels: twice the flow of the parent pixel (clamped to the coarse
-// grid).  Cost re-evaluated.  grid (pixels / 256, 2 * pairs).
+// grid).  Cost re-evaluated on the descriptors or, with census set, on the
+// Census strings.  grid (pixels / 256, 2 * pairs).
 __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs, int level, int coarsest,
-                                              int stride)
+                                              int stride, int census)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
@@ -532,7 +665,8 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
         const uint32_t cf = (uint32_t)C.state[dir][(size_t)cy * C.W + cx].x;
         f = pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
     }
-    const int32_t c = cost_at((gcu8*)L.desc[dir ^ 1], W, H, x, y, f, load_desc((gcu8*)L.desc[dir], i));
+    const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
+                             : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
     L.state[dir][i] = make_int2((int)f, c);
 }
 
@@ -586,7 +720,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // gathered at its end and selected during window w+1's first relaxation
 // round, so their memory latency overlaps other work.  The trials, their
 // order and the selection rule are those of random_search().
-template <int RC, bool COL, int CH>
+template <int RC, bool COL, int CH, int CK>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
                                                     bool lin, bool lout, li2* lline, int W, int H, int len, int line,
@@ -594,6 +728,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
                                                     const SearchConst& sc)
 {
+    using FT = typename Feat<CK>::T;
     constexpr int WIN = 64 * CH;
     constexpr int JC = 31 - __builtin_clz((unsigned)RC) + 1;
     const int nwin = (len + WIN - 1) / WIN;
@@ -601,14 +736,14 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
 
     uint32_t f0[CH], nf0[CH];
     int32_t c0[CH], nc0[CH];
-    uint4 a[CH], na[CH];
-    auto load_window = [&](int w0, uint32_t* F, int32_t* C, uint4* A) {
+    FT a[CH], na[CH];
+    auto load_window = [&](int w0, uint32_t* F, int32_t* C, FT* A) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             const int p = w0 + 64 * c + lane;
             const bool valid = p < len;
             const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
-            A[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
+            A[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
             F[c] = (uint32_t)st.x;
             C[c] = st.y;
         }
@@ -620,7 +755,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
     int pw0 = 0;
     uint32_t pbf[CH], pcand[CH][JC];
     int32_t pbc[CH];
-    uint4 pdesc[CH][JC], pa[CH];
+    FT pdesc[CH][JC], pa[CH];
     uint32_t pin[CH];                                            // bit j: trial j lands inside image B
     auto finish = [&]() {
 #pragma unroll
@@ -631,7 +766,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
             int32_t bc = pbc[c];
 #pragma unroll
             for (int j = 0; j < JC; ++j) {
-                const int32_t e = ((pin[c] >> j) & 1u) ? sad16(pa[c], pdesc[c][j]) : kInf;
+                const int32_t e = ((pin[c] >> j) & 1u) ? Feat<CK>::dist(pa[c], pdesc[c][j]) : kInf;
                 if (e < bc) { bc = e; bf = pcand[c][j]; }
             }
             if (lout) lline[p] = i32x2{(int)bf, bc};
@@ -681,7 +816,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                         const int p = w0 + 64 * c + lane;
                         lp[c] = pred[c];
                         le[c] = pred[c] == f0[c] ? c0[c]
-                                                 : cost_at<COL>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
+                                                 : feat_cost<COL, CK>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
                     }
                 }
             }
@@ -723,7 +858,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     // running best's upper bound: never selected, not gathered
                     const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H && (qdx | qdy) != 0;
                     pin[c] |= in ? (1u << j) : 0u;
-                    pdesc[c][j] = in ? ld16(DB + pix<COL>(qx, qy, W, H) * 16) : make_uint4(0, 0, 0, 0);
+                    pdesc[c][j] = in ? Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)) : Feat<CK>::zero();
                 }
             }
             pend = true;
@@ -759,10 +894,13 @@ struct StageDims {
     static constexpr int CAP = RI * RJ;
 };
 
-template <int RC, bool COL, int CH, int WPB, bool STG>
+template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
                                                          int iter, int upto, SearchConst sc, int xw)
 {
+    static_assert(!STG || CK == 0, "the staged random search holds descriptors");
+    using FT = typename Feat<CK>::T;
+    constexpr size_t FB = CK ? 8 : 16;                           // feature bytes per pixel
     const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int pd = lb / gridDim.x, bx = lb % gridDim.x;
     const PairDev& P = pairs[pd >> 1];
@@ -785,8 +923,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
-    gcu8* __restrict__ DA = (gcu8*)(COL ? L.descT[dir] : L.desc[dir]) + (size_t)line * len * 16;
-    gcu8* __restrict__ DB = (gcu8*)(COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]);
+    gcu8* __restrict__ DA = (gcu8*)(CK ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
+                            (size_t)line * len * FB;
+    gcu8* __restrict__ DB = (gcu8*)(CK ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
+                                       : (COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]));
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
     constexpr int WIN = 64 * CH;
     const int nwin = (len + WIN - 1) / WIN;
@@ -832,7 +972,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
 
         if constexpr (!STG && RC > 0 && CH <= 2) {
             if (active)
-                line_pass_pipelined<RC, COL, CH>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
+                line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
                                                  (uint32_t)level, ctr2, sc);
             continue;
         }
@@ -841,14 +981,14 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             const int w0 = (fwd ? wi : nwin - 1 - wi) * WIN;
             uint32_t f0[CH], lp[CH], h[CH];
             int32_t c0[CH], le[CH];
-            uint4 a[CH];
+            FT a[CH];
             bool hp[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = active && p < len;
                 const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
-                a[c] = valid ? load_desc(DA, p) : make_uint4(0, 0, 0, 0);
+                a[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
                 f0[c] = (uint32_t)st.x;
                 c0[c] = st.y;
                 hp[c] = valid && (fwd ? p > 0 : p + 1 < len);
@@ -931,7 +1071,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                         const int p = w0 + 64 * c + lane;
                         lp[c] = pred[c];
                         le[c] = pred[c] == f0[c] ? c0[c]
-                                                 : cost_at<COL>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
+                                                 : feat_cost<COL, CK>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
                     }
                 }
 #pragma unroll
@@ -953,8 +1093,8 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                 int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
                 const int x = COL ? line : p, y = COL ? p : line;
                 if (rs) {
-                    const uint4 ac = a[c];
-                    if (STG) {
+                    const FT ac = a[c];
+                    if constexpr (STG) {
                         random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc, [&](uint32_t f) -> int32_t {
                             const int qx = x + flow_x(f), qy = y + flow_y(f);
                             if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
@@ -965,7 +1105,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                         });
                     } else {
                         random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc,
-                                          [&](uint32_t f) { return cost_at<COL>(DB, W, H, x, y, f, ac); });
+                                          [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, x, y, f, ac); });
                     }
                 }
                 if (lout) lline[p] = i32x2{(int)bf, bc};
@@ -1157,6 +1297,11 @@ void launch_desc(const PairDev* d, int npairs, int level, int maxW, int maxH, hi
     hipLaunchKernelGGL(k_desc, dim3((maxW + kDescTX - 1) / kDescTX, (maxH + kDescTY - 1) / kDescTY, 2 * npairs),
                        dim3(256), 0, st, d, level);
 }
+void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_census, dim3((maxW + kCenTX - 1) / kCenTX, (maxH + kCenTY - 1) / kCenTY, 2 * npairs),
+                       dim3(256), 0, st, d, level);
+}
 void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
 {
     hipLaunchKernelGGL(k_seed_records, dim3((maxN + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
@@ -1177,9 +1322,11 @@ void launch_seed_nn(const PairDev* d, int npairs, int level, int stride, int max
     hipLaunchKernelGGL(k_seed_nn<MQ>, dim3((qwaves + 3) / 4, splits, 2 * npairs), dim3(256), 0, st, d, level,
                        stride, tps);
 }
-void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stride, int maxpx, hipStream_t st)
+void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stride, int census, int maxpx,
+                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride);
+    hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride,
+                       census);
 }
 // A line phase keeps its WPB lines' state in LDS between its passes when
 // they fit in 64 KiB (lines up to 1024 px at 8 lines per block, 2048 px at 4).
@@ -1188,50 +1335,61 @@ bool line_cross_write(int wpb, int maxlen)
     return (size_t)wpb * (size_t)maxlen * sizeof(int2) <= 65536;
 }
 
-template <int RC, bool COL, int CH, int WPB, bool STG>
+template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
                    int maxlen, hipStream_t st)
 {
     const int xw = line_cross_write(WPB, maxlen) ? 1 : 0;
     const size_t dyn = xw ? (size_t)WPB * maxlen * sizeof(int2) : 0;
-    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
+    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
                        dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw);
 }
 
-template <int RC, bool COL>
+template <int RC, bool COL, int CK>
 bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
                     const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
 {
-#define FF_LINE_CASE(C, B, G)                                                                 \
-    if (ch == C && wpb == B && stg == G) {                                                    \
-        launch_line_t<RC, COL, C, B, G != 0>(d, npairs, level, iter, upto, sc, nlines, maxlen, st); \
-        return true;                                                                          \
+#define FF_LINE_CASE(C, B, G)                                                                        \
+    if (ch == C && wpb == B && stg == G) {                                                           \
+        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, st); \
+        return true;                                                                                 \
     }
     FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
     FF_LINE_CASE(2, 2, 0) FF_LINE_CASE(2, 4, 0) FF_LINE_CASE(2, 8, 0)
     FF_LINE_CASE(4, 2, 0) FF_LINE_CASE(4, 4, 0) FF_LINE_CASE(4, 8, 0)
     FF_LINE_CASE(8, 2, 0) FF_LINE_CASE(8, 4, 0) FF_LINE_CASE(8, 8, 0)
-    FF_LINE_CASE(1, 4, 1) FF_LINE_CASE(1, 8, 1) FF_LINE_CASE(1, 16, 1) FF_LINE_CASE(2, 8, 1)
+    if constexpr (CK == 0) {
+        FF_LINE_CASE(1, 4, 1) FF_LINE_CASE(1, 8, 1) FF_LINE_CASE(1, 16, 1) FF_LINE_CASE(2, 8, 1)
+    }
 #undef FF_LINE_CASE
     return false;
 }
 
+template <int CK>
+bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
+                    int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
+{
+    if (sc.radius == 16)
+        return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
+                   : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+    return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
+               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+}
+
 // One row or column phase of every pair and direction at one level.  ch =
 // chunks of 64 px per relaxation window, wpb = lines per block, stg = staged
-// random search; supported: stg 0 with ch in {1, 2, 4, 8} and wpb in {2, 4, 8}
-// (ch <= 2 runs the software-pipelined pass at radius 16); stg 1 with
+// random search, census = Census cost (else descriptor SAD); supported: stg 0
+// with ch in {1, 2, 4, 8} and wpb in {2, 4, 8} (ch <= 2 runs the
+// software-pipelined pass at radius 16); stg 1, descriptor cost only, with
 // (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false otherwise.
 // nlines / maxlen: the batch's largest line count and line length.  The
 // column phase reads the row-major state and, when line_cross_write()
 // allows it, also writes it (otherwise its result stays in stateT).
-bool launch_line_phase(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
-                       int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
+bool launch_line_phase(bool col, int ch, int wpb, int stg, bool census, const PairDev* d, int npairs, int level,
+                       int iter, int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
 {
-    if (sc.radius == 16)
-        return col ? launch_line_rc<16, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
-                   : launch_line_rc<16, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
-    return col ? launch_line_rc<0, true>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
-               : launch_line_rc<0, false>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+    return census ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
+                  : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

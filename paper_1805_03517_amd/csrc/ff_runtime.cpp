@@ -29,8 +29,9 @@ void launch_down2(const PairDev*, int, int, int, hipStream_t);
 void launch_desc(const PairDev*, int, int, int, int, hipStream_t);
 void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
-void launch_init(const PairDev*, int, int, int, int, int, hipStream_t);
-bool launch_line_phase(bool, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, int,
+void launch_init(const PairDev*, int, int, int, int, int, int, hipStream_t);
+void launch_census(const PairDev*, int, int, int, int, hipStream_t);
+bool launch_line_phase(bool, int, int, int, bool, const PairDev*, int, int, int, int, const SearchConst&, int, int,
                        hipStream_t);
 bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
@@ -158,6 +159,7 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
         b += 2 * align_up(n);            // gray planes
         b += 4 * align_up(n * 16);       // descriptors, row- and column-major
         b += 4 * align_up(n * 8);        // state, row- and column-major
+        if (p.flags & FF_COST_CENSUS) b += 4 * align_up(n * 8);   // Census strings, both layouts
     }
     const int c = p.levels - 1;
     pl.nsx = (pl.W[c] + p.seed_stride - 1) / p.seed_stride;
@@ -176,7 +178,7 @@ ff_status validate_params(ff_ctx* h, const ff_params& p)
     if (p.iters < 0 || p.iters > 64) return fail(h, FF_ERR_INVALID, "iters must be in 0..64");
     if (p.rs_radius < 0 || p.rs_radius > 1024) return fail(h, FF_ERR_INVALID, "rs_radius must be in 0..1024");
     if (p.fb_eps < 0 || p.fb_eps > 1024) return fail(h, FF_ERR_INVALID, "fb_eps must be in 0..1024");
-    if (p.flags & ~FF_SPARSIFY) return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS)) return fail(h, FF_ERR_INVALID, "unknown flag bits");
     if ((p.flags & FF_SPARSIFY) && (p.sparse_min < 1 || p.sparse_min > 9))
         return fail(h, FF_ERR_INVALID, "sparse_min must be in 1..9");
     return FF_OK;
@@ -267,6 +269,10 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
             for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(np * 16);
             for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take(np * 8);
             for (int k = 0; k < 2; ++k) L.stateT[k] = (int2*)take(np * 8);
+            if (p.flags & FF_COST_CENSUS) {
+                for (int k = 0; k < 2; ++k) L.cen[k] = (uint8_t*)take(np * 8);
+                for (int k = 0; k < 2; ++k) L.cenT[k] = (uint8_t*)take(np * 8);
+            }
         }
         const int c = p.levels - 1;
         for (int k = 0; k < 2; ++k) d.dbrec[k] = (int8_t*)take((size_t)pl.W[c] * pl.H[c] * 64);
@@ -345,9 +351,9 @@ SearchConst search_const(const ff_params& p)
 }
 
 const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn",
-                                    "init", "row_phase", "col_phase", "transpose", "fb", "sparse"};
+                                    "init", "row_phase", "col_phase", "transpose", "fb", "sparse", "census"};
 enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_SPARSE,
-       KN_COUNT };
+       KN_CENSUS, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
@@ -408,6 +414,14 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         return FF_OK;
     }
     for (int l = 0; l < L; ++l) FF_TRACED(KN_DESC, l, launch_desc(d, n, l, D.maxW[l], D.maxH[l], st));
+    const bool census = (p.flags & FF_COST_CENSUS) != 0;
+    if (census)
+        for (int l = 0; l < L; ++l) FF_TRACED(KN_CENSUS, l, launch_census(d, n, l, D.maxW[l], D.maxH[l], st));
+    if (stop.active && stop.st.kind == FF_STAGE_CENSUS) {
+        const int l = stop.st.level;
+        FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].cen[stop.st.image], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
+        return FF_OK;
+    }
     if (stop.active && stop.st.kind == FF_STAGE_DESC) {
         const int l = stop.st.level;
         launch_copy_desc_signed(tab0->lv[l].desc[stop.st.image], (int8_t*)stop.dst, level_px(l) * 16, st);
@@ -420,7 +434,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         return FF_OK;
     }
     for (int l = c; l >= 0; --l) {
-        FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, D.maxPx[l], st));
+        FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
         const bool stop_here = stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
         if (stop_here && stop.st.step == 0) {
             FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
@@ -429,12 +443,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         for (int t = 0; t < p.iters; ++t) {
             const bool last = stop_here && stop.st.iter == t;
             const int upto = last ? stop.st.step : 7;
-            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], d, n, l, t,
+            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census, d, n, l, t,
                                                 std::min(upto, 3), sc, D.maxH[l], D.maxW[l], st));
             if (upto >= 4) {
                 // the column phase reads the row-major state; its result comes
                 // back row-major when the cross write applies, else from stateT
-                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], d, n, l, t, upto, sc,
+                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census, d, n, l, t, upto, sc,
                                                     D.maxW[l], D.maxH[l], st));
                 if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
                     FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
@@ -614,6 +628,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
     std::vector<Timed> discard;
     (void)collect_profile(h, discard);
     for (const auto& c : kCand) {
+        if (c[2] && (h->prm.flags & FF_COST_CENSUS)) continue;   // staged: descriptor cost only
         drop_graphs(h);
         for (int ph = 0; ph < 2; ++ph)
             for (int l = 0; l < L; ++l) {
@@ -843,10 +858,12 @@ ff_status ff_debug_stage(ff_handle h, const ff_pair* pair, const ff_stage* which
     if (!h) return FF_ERR_INVALID;
     if (!pair || !which || !dst) return fail(h, FF_ERR_INVALID, "pair, which and dst are required");
     const ff_stage& w = *which;
-    if (w.kind < FF_STAGE_GRAY || w.kind > FF_STAGE_STATE || w.image < 0 || w.image > 1 || w.dir < 0 ||
+    if (w.kind < FF_STAGE_GRAY || w.kind > FF_STAGE_CENSUS || w.image < 0 || w.image > 1 || w.dir < 0 ||
         w.dir > 1 || w.level < 0 || w.level >= h->prm.levels || w.step < 0 || w.step > 7 || w.iter < 0 ||
         (w.kind == FF_STAGE_STATE && w.step > 0 && w.iter >= h->prm.iters))
         return fail(h, FF_ERR_INVALID, "bad debug stage");
+    if (w.kind == FF_STAGE_CENSUS && !(h->prm.flags & FF_COST_CENSUS))
+        return fail(h, FF_ERR_INVALID, "Census strings exist only with FF_COST_CENSUS");
     Stop s;
     s.active = true;
     s.st = w;
@@ -924,6 +941,8 @@ ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n)
         const bool plain = stg == 0 && (ch == 1 || ch == 2 || ch == 4 || ch == 8) && (wpb == 2 || wpb == 4 || wpb == 8);
         const bool staged = stg == 1 && ((ch == 1 && (wpb == 4 || wpb == 8 || wpb == 16)) || (ch == 2 && wpb == 8));
         if (!plain && !staged) return fail(h, FF_ERR_INVALID, "unsupported (chunks, lines, staged) triple");
+        if (staged && (h->prm.flags & FF_COST_CENSUS))
+            return fail(h, FF_ERR_INVALID, "staged schedules need the descriptor cost");
     }
     for (int ph = 0; ph < 2; ++ph)
         for (int l = 0; l < L; ++l) {

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(PKG, "libff.so")
 
 FF_OK, FF_ERR_INVALID, FF_ERR_OOM, FF_ERR_BUDGET, FF_ERR_HIP, FF_ERR_UNSUPPORTED, FF_ERR_BUSY = range(7)
 FF_SPARSIFY = 1                                  # params.flags: 3x3-block sparsification
-STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE = range(5)
+FF_COST_CENSUS = 2                               # params.flags: 7x7 Census (Hamming) matching cost
+STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE, STAGE_CENSUS = range(6)
 INF = 2**31 - 1
 
 # Every symbol include/ff.h declares, in declaration order.
@@ -115,16 +116,20 @@ class Matcher:
     [H, W] (gray) or [H, W, 3] (RGB), contiguous."""
 
     def __init__(self, levels=4, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
-                 hbm_budget=0, device=0, sparse_min=0):
+                 hbm_budget=0, device=0, sparse_min=0, cost="wh"):
         """sparse_min > 0 turns on the 3x3-block sparsification (FF_SPARSIFY)
         with that minimum number of matches s; outputs then include
-        sparse_f / sparse_b and the consistency errors fberr_f / fberr_b."""
+        sparse_f / sparse_b and the consistency errors fberr_f / fberr_b.
+        cost: "wh" (descriptor SAD) or "census" (7x7 Census Hamming distance,
+        FF_COST_CENSUS)."""
+        if cost not in ("wh", "census"):
+            raise FFError(FF_ERR_INVALID, "cost must be 'wh' or 'census'")
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
         self.sparse = sparse_min > 0
-        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget,
-                             FF_SPARSIFY if self.sparse else 0, sparse_min)
+        flags = (FF_SPARSIFY if self.sparse else 0) | (FF_COST_CENSUS if cost == "census" else 0)
+        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget, flags, sparse_min)
         h = ctypes.c_void_p()
         st = lib().ff_create(ctypes.byref(self.params), device, ctypes.byref(h))
         if st != FF_OK:
@@ -215,6 +220,8 @@ class Matcher:
             dst = t.empty((-(-Hc // s), -(-Wc // s)), dtype=t.int32, device=self.device)
         elif kind == STAGE_STATE:
             dst = t.empty((Hl, Wl, 2), dtype=t.int32, device=self.device)
+        elif kind == STAGE_CENSUS:
+            dst = t.empty((Hl, Wl), dtype=t.int64, device=self.device)
         else:
             raise FFError(FF_ERR_INVALID, "unknown stage kind")
         o = self._outputs(H, W, True, True)
