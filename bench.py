@@ -227,6 +227,55 @@ def sparse_bench(torch, ff, pairs, steps):
                        "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}}
 
 
+CEN_COL_BYTES_PER_PX = 12 * 8 + 32     # 12 Census gathers of 8 B, own strings 2 x 8, state in + out
+
+
+def census_bench(torch, ff, n_pairs, distinct, steps):
+    """Census cost (Sec. 3.1; the paper's Sintel cost, eps = 7 from Table 3)
+    on a batch of Sintel-shaped 1024x436 RGB pairs, against the descriptor
+    cost on the same batch; each with the schedule ff_autotune picks for it.
+    Census col-phase algorithmic bytes per pixel, direction and iteration:
+    12 candidate gathers x 8 B + own strings 2 x 8 B + state 8 B in and out."""
+    from paper_1805_03517_amd import synth
+    W, H = 1024, 436
+    base = [synth.config2(seed=30 + k)[:2] for k in range(distinct)]
+    pairs = [(torch.from_numpy(base[k % distinct][0]).cuda(), torch.from_numpy(base[k % distinct][1]).cuda())
+             for k in range(n_pairs)]
+    dims = level_dims(W, H, LEVELS)
+    px_all = sum(w * h for w, h in dims)
+    out = {"workload": f"{n_pairs} Sintel-shaped {W}x{H} RGB pairs ({distinct} distinct), L = {LEVELS}, eps = 7"}
+    for cost in ("census", "wh"):
+        m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=7, seed=0x5EED, cost=cost)
+        outs = [m._outputs(H, W, True, True) for _ in pairs]
+        m.match_batch(pairs, outs=outs)
+        tuning = m.autotune(pairs, outs=outs)
+        for _ in range(2):
+            m.match_batch(pairs, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            m.match_batch(pairs, outs=outs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        m.profile(True)
+        for _ in range(steps):
+            m.match_batch(pairs, outs=outs)
+        prof = m.profile_read()
+        m.profile(False)
+        m.close()
+        n, ms = prof["col_phase"]
+        per_px = CEN_COL_BYTES_PER_PX if cost == "census" else COL_BYTES_PER_PX
+        avg_bytes = per_px * px_all * 2 * n_pairs * 2 / (2 * LEVELS)
+        avg_s = ms / n / 1000.0
+        gbs = avg_bytes / avg_s / 1e9
+        out[cost] = {"pairs_per_s": n_pairs * steps / wall, "px_per_s": n_pairs * steps * W * H / wall,
+                     "ms_per_step": 1000.0 * wall / steps, "schedule": tuning,
+                     "col_phase": {"avg_us": avg_s * 1e6, "algorithmic_bytes_per_launch": avg_bytes,
+                                   "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
+                     "kernels": {k: round(1000.0 * v[1] / max(v[0], 1), 1) for k, v in prof.items()}}
+    return out
+
+
 def c4_bench(torch, ff, n_pairs):
     """Config 4: n uneven gray pairs (sides 96..256, translations up to
     +-24 px, 3 levels) as ONE batched call (replayed hipGraph, tuned schedule)
@@ -284,6 +333,7 @@ def main():
     ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-census", action="store_true", help="skip the Census-cost leg")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
@@ -388,6 +438,11 @@ def main():
     print("[bench] sparsification leg", file=sys.stderr, flush=True)
     sparse = sparse_bench(torch, ff, pairs, max(2, args.steps // 4))
 
+    census = None
+    if not args.no_census:
+        print("[bench] Census-cost leg (Sintel-shaped batch)", file=sys.stderr, flush=True)
+        census = census_bench(torch, ff, args.batch, args.distinct, max(2, args.steps // 4))
+
     serving = None
     if not args.no_serve:
         print(f"[bench] serving: {args.serve_requests} mixed requests, served vs plain", file=sys.stderr, flush=True)
@@ -433,6 +488,7 @@ def main():
         "plain": plain,
         "seed_nn": seednn,
         "sparsify": sparse,
+        "census": census,
         "serving": serving,
         "batch_c4": batch_c4,
         "cpu_baseline": cpu,

@@ -413,8 +413,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].gray[stop.st.image], level_px(l), hipMemcpyDeviceToDevice, st));
         return FF_OK;
     }
-    for (int l = 0; l < L; ++l) FF_TRACED(KN_DESC, l, launch_desc(d, n, l, D.maxW[l], D.maxH[l], st));
     const bool census = (p.flags & FF_COST_CENSUS) != 0;
+    // with the Census cost only the seed level needs descriptors (unless a
+    // debug stop asks for another level's)
+    for (int l = 0; l < L; ++l)
+        if (!census || l == c || (stop.active && stop.st.kind == FF_STAGE_DESC))
+            FF_TRACED(KN_DESC, l, launch_desc(d, n, l, D.maxW[l], D.maxH[l], st));
     if (census)
         for (int l = 0; l < L; ++l) FF_TRACED(KN_CENSUS, l, launch_census(d, n, l, D.maxW[l], D.maxH[l], st));
     if (stop.active && stop.st.kind == FF_STAGE_CENSUS) {
