@@ -35,7 +35,8 @@ def build(force: bool = True) -> str:
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("seed_stride", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
-                ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("cost_kind", ctypes.c_int32)]
+                ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("cost_kind", ctypes.c_int32),
+                ("two_checks", ctypes.c_int32), ("seed2", ctypes.c_uint64)]
 
 
 COST_WH, COST_CENSUS = 0, 1
@@ -63,6 +64,7 @@ def lib():
         l.ffo_nearest.argtypes = [P, P, i]
         l.ffo_fb_error.argtypes = [i, i, P, P, P, P, P]
         l.ffo_sparsify.argtypes = [i, i, P, P, i, P]
+        l.ffo_fb_error2.argtypes = [i, i, P, P, P, P, P, P, P]
         l.ffo_census.argtypes = [P, i, i, P]
         l.ffo_cost_census.argtypes = [P, P, i, i, i, i, i, i]
         l.ffo_cost_census.restype = ctypes.c_int32
@@ -85,8 +87,9 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, cost_kind=COST_WH) -> Params:
-    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind)
+def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, cost_kind=COST_WH,
+           two_checks=0, seed2=0) -> Params:
+    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind, two_checks, seed2)
 
 
 def gray(img: np.ndarray) -> np.ndarray:
@@ -223,6 +226,17 @@ def fb_error(F, cF, B, cB) -> np.ndarray:
     H, W = cF.shape
     out = np.empty((H, W), np.int32)
     lib().ffo_fb_error(W, H, _p(F), _p(cF), _p(B), _p(cB), _p(out))
+    return out
+
+
+def fb_error2(F, cF, B1, cB1, B2, cB2) -> np.ndarray:
+    """Sec. 3.1 two consistency checks: the larger of the errors against the
+    inverse fields B1 and B2 (INF when either is)."""
+    a = [np.ascontiguousarray(v, dtype=np.int16) for v in (F, B1, B2)]
+    c = [np.ascontiguousarray(v, dtype=np.int32) for v in (cF, cB1, cB2)]
+    H, W = c[0].shape
+    out = np.empty((H, W), np.int32)
+    lib().ffo_fb_error2(W, H, _p(a[0]), _p(c[0]), _p(a[1]), _p(c[1]), _p(a[2]), _p(c[2]), _p(out))
     return out
 
 

@@ -474,6 +474,18 @@ void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
         }
 }
 
+/* Two consistency checks (Sec. 3.1): the larger of the two errors.       */
+void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,
+                   const int16_t* B2, const int32_t* cB2, int32_t* err)
+{
+    int32_t* e2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)W * H);
+    ffo_fb_error(W, H, F, cF, B1, cB1, err);
+    ffo_fb_error(W, H, F, cF, B2, cB2, e2);
+    for (size_t p = 0; p < (size_t)W * H; ++p)
+        if (e2[p] > err[p]) err[p] = e2[p];
+    free(e2);
+}
+
 /* Sparsification (Sec. 3.1, s from Table 3): one kept match per 3x3 block
  * holding at least s consistent matches -- the lowest consistency error,
  * scanning the block in row-major order so the first minimum is the lowest
@@ -545,8 +557,31 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
     search_direction(p, lv, 0, 1, 0, flow_f, cf, trace, user);
     search_direction(p, lv, 1, 0, 1, fb, cb, trace, user);
 
-    consistency(W, H, p->fb_eps, flow_f, cf, fb, cb, mask_f);
-    if (mask_b) consistency(W, H, p->fb_eps, fb, cb, flow_f, cf, mask_b);
+    if (!p->two_checks) {
+        consistency(W, H, p->fb_eps, flow_f, cf, fb, cb, mask_f);
+        if (mask_b) consistency(W, H, p->fb_eps, fb, cb, flow_f, cf, mask_b);
+    } else {
+        /* second pair of fields: the same search keyed by seed2; a match
+         * must be consistent with both inverse fields (Sec. 3.1)          */
+        ffo_params p2 = *p;
+        p2.seed = p->seed2;
+        size_t n = (size_t)W * H;
+        int16_t* f2 = (int16_t*)malloc(sizeof(int16_t) * 2 * n);
+        int16_t* b2 = (int16_t*)malloc(sizeof(int16_t) * 2 * n);
+        int32_t* cf2 = (int32_t*)malloc(sizeof(int32_t) * n);
+        int32_t* cb2 = (int32_t*)malloc(sizeof(int32_t) * n);
+        int32_t* e = (int32_t*)malloc(sizeof(int32_t) * n);
+        search_direction(&p2, lv, 0, 1, 0, f2, cf2, NULL, NULL);
+        search_direction(&p2, lv, 1, 0, 1, b2, cb2, NULL, NULL);
+        int eps2 = p->fb_eps * p->fb_eps;
+        ffo_fb_error2(W, H, flow_f, cf, fb, cb, b2, cb2, e);
+        for (size_t q = 0; q < n; ++q) mask_f[q] = e[q] <= eps2 ? 1 : 0;
+        if (mask_b) {
+            ffo_fb_error2(W, H, fb, cb, flow_f, cf, f2, cf2, e);
+            for (size_t q = 0; q < n; ++q) mask_b[q] = e[q] <= eps2 ? 1 : 0;
+        }
+        free(f2); free(b2); free(cf2); free(cb2); free(e);
+    }
 
     if (!cost_f) free(cf);
     if (!flow_b) free(fb);

@@ -31,6 +31,9 @@ typedef struct {
     int32_t  fb_eps;        /* consistency threshold epsilon in px (1)       */
     uint64_t seed;          /* random-search key                             */
     int32_t  cost_kind;     /* FFO_COST_WH (0) or FFO_COST_CENSUS (1)         */
+    int32_t  two_checks;    /* 1: masks need a second check against the
+                               inverse fields of a search keyed by seed2      */
+    uint64_t seed2;         /* random-search key of the second search        */
 } ffo_params;
 
 #define FFO_COST_WH     0   /* SAD of the 16 Walsh-Hadamard coefficients     */
@@ -96,6 +99,13 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
  * FFO_INF otherwise.  The consistency mask is exactly err <= eps^2.       */
 void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
                   const int16_t* B, const int32_t* cB, int32_t* err);
+
+/* Two consistency checks (Sec. 3.1): F against two inverse fields B1 and B2
+ * computed with different matching parameters.  err = the larger of the two
+ * errors (FFO_INF when either is); a match passes both checks exactly when
+ * err <= eps^2.                                                            */
+void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,
+                   const int16_t* B2, const int32_t* cB2, int32_t* err);
 
 /* Sparsification (Sec. 3.1; minimum matches s from Table 3): the image is
  * cut into 3x3 blocks from the origin, the last column and row of blocks

@@ -199,6 +199,45 @@ def test_fb_error_thresholds_reproduce_the_mask(orc, eps):
     assert (ef[r["cost_f"] == orc.INF] == orc.INF).all()
 
 
+def test_fb_error2_worked_example_and_reduction(orc):
+    F = np.array([[[1, 0], [0, 0], [-1, 0], [0, 0]]], np.int16)
+    cF = np.array([[10, 3, 3, 7]], np.int32)
+    B1 = np.array([[[0, 0], [-1, 1], [0, 0], [0, 1]]], np.int16)
+    cB1 = np.array([[0, 2, 0, 5]], np.int32)
+    B2 = np.array([[[0, 0], [1, -1], [3, 0], [0, 0]]], np.int16)
+    cB2 = np.array([[0, 2, 0, orc.INF]], np.int32)
+    # p0 -> q = 1: e1 = (1-1)^2 + (0+1)^2 = 1, e2 = (1+1)^2 + (0-1)^2 = 5
+    # p1 -> q = 1: e1 = 1 + 1 = 2, e2 = 1 + 1 = 2; p2 -> q = 1: e1 = 4 + 1 = 5, e2 = 0 + 1 = 1
+    # p3 -> q = 3: second inverse match invalid -> INF
+    err = orc.fb_error2(F, cF, B1, cB1, B2, cB2)
+    assert err.tolist() == [[5, 2, 5, orc.INF]]
+    i1, i2, _ = synth.config0()
+    r = orc.match(i1, i2, orc.params(levels=3))
+    one = orc.fb_error(r["flow_f"], r["cost_f"], r["flow_b"], r["cost_b"])
+    two = orc.fb_error2(r["flow_f"], r["cost_f"], r["flow_b"], r["cost_b"], r["flow_b"], r["cost_b"])
+    assert np.array_equal(one, two)                      # the same inverse field twice = one check
+
+
+def test_two_checks_in_the_search(orc):
+    """Two checks leave flows and costs alone, equal one check when the
+    second search has the same key, and otherwise keep a subset of the
+    one-check matches: exactly those consistent with both inverse fields."""
+    i1, i2, _ = synth.config0()
+    one = orc.match(i1, i2, orc.params(levels=3))
+    same = orc.match(i1, i2, orc.params(levels=3, two_checks=1, seed2=0x5EED))
+    for k in one:
+        assert np.array_equal(one[k], same[k]), k
+    two = orc.match(i1, i2, orc.params(levels=3, two_checks=1, seed2=0xBEEF))
+    for k in ("flow_f", "cost_f", "flow_b", "cost_b"):
+        assert np.array_equal(one[k], two[k]), k
+    for k in ("mask_f", "mask_b"):
+        assert not (two[k] & (1 - one[k])).any()
+    assert two["mask_f"].sum() < one["mask_f"].sum()       # the second check removes something
+    alt = orc.match(i1, i2, orc.params(levels=3, seed=0xBEEF))
+    e = orc.fb_error2(one["flow_f"], one["cost_f"], one["flow_b"], one["cost_b"], alt["flow_b"], alt["cost_b"])
+    assert np.array_equal(two["mask_f"], (e <= 1).astype(np.uint8))
+
+
 def _read_sparse_fixture():
     lines = [l.strip() for l in open(os.path.join(HERE, "golden", "sparsify_3x3_example.txt"))]
     rows = [l for l in lines if l and not l.startswith("#") and not l.startswith("s ")]
