@@ -26,6 +26,8 @@
  *     from Philox4x32-10 at counter (y*W+x, level, iter<<2|pass, j>>1) and
  *     key (seed low, seed high), accepted on a strictly lower cost;
  *   - mask(p) = 1 iff both matches are valid and |F(p) + B(p + F(p))|^2 <= eps^2;
+ *     with FF_SECOND_CHECK also against B2, the inverse field of the same
+ *     search keyed by seed2, the error then being the larger of the two;
  *   - optionally (FF_SPARSIFY, Sec. 3.1 with s from Table 3): in every 3x3
  *     block from the origin (partial at the borders) holding at least s
  *     consistent matches, only the match with the lowest consistency error
@@ -66,6 +68,9 @@ typedef enum {
 #define FF_COST_CENSUS 2u   /* matching cost = Hamming distance of 7x7 Census strings
                                (Sec. 3.1) instead of descriptor SAD; seeds still
                                match descriptors; staged schedules unsupported     */
+#define FF_SECOND_CHECK 4u  /* two consistency checks (Sec. 3.1): the search runs a
+                               second time keyed by seed2, and a match must also be
+                               consistent with that search's inverse field        */
 
 /* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 and s = 7 for
  * KITTI, epsilon = 7 and s = 4 for MPI Sintel). */
@@ -77,9 +82,11 @@ typedef struct {
     int32_t  fb_eps;        /* consistency threshold in px, 0..1024 (1)          */
     uint64_t seed;          /* random-search key                                 */
     uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
-    uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS, or 0                */
+    uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK, or 0 */
     int32_t  sparse_min;    /* s: matches a 3x3 block needs to keep one, 1..9
                                (7); read only with FF_SPARSIFY                 */
+    uint64_t seed2;         /* random-search key of the second search; read
+                               only with FF_SECOND_CHECK                       */
 } ff_params;
 
 /* One image pair and its outputs.  Both frames are [H][W][C] uint8,

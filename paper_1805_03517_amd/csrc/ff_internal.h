@@ -47,6 +47,7 @@ struct PairDev {
     uint8_t* mask[2];
     int32_t* fberr[2];               // consistency error (caller's buffer, or the workspace's when sparsifying)
     uint8_t* sparse[2];              // 3x3-block selection (caller's); null = not computed
+    int2* save[2];                   // first search's level-0 state (second consistency check)
 };
 
 struct SearchConst {

@@ -1219,6 +1219,52 @@ __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, i
     }
 }
 
+// --------------------------------------------- second consistency check --
+// Keep the first search's level-0 state while the second search (keyed by
+// seed2) reuses the state planes.  grid (pixels / 256, 2 * pairs).
+__global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ pairs)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[0];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= L.W * L.H) return;
+    ((gi2*)P.save[dir])[i] = ((const gi2*)L.state[dir])[i];
+}
+
+// Two consistency checks (Sec. 3.1): p of the first search's field F is
+// checked against the first search's inverse field B and the second
+// search's B2; the error is the larger of the two (INF when either match is
+// invalid) and the mask is error <= eps^2.  Flow and cost come from the first
+// search.  Four pixels per thread as k_fb.  grid (pixels / 1024, 2 * pairs).
+__global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[0];
+    const int W = L.W, n = L.W * L.H;
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    const gi2* __restrict__ own = (const gi2*)P.save[dir];
+    const gi2* __restrict__ inv1 = (const gi2*)P.save[dir ^ 1];
+    const gi2* __restrict__ inv2 = (const gi2*)L.state[dir ^ 1];
+    uint32_t* fl = reinterpret_cast<uint32_t*>(P.flow[dir]);
+    int32_t* co = P.cost[dir];
+    uint8_t* mk = P.mask[dir];
+    int32_t* er = P.fberr[dir];
+    int y = i0 / W, x = i0 - y * W;
+    for (int i = i0; i < min(i0 + 4, n); ++i) {
+        const i32x2 st = own[i];
+        const int32_t e1 = fb_err(inv1, W, x, y, st), e2 = fb_err(inv2, W, x, y, st);
+        const int32_t e = max(e1, e2);
+        if (fl) fl[i] = (uint32_t)st.x;
+        if (co) co[i] = st.y;
+        if (mk) mk[i] = e <= eps2 ? 1 : 0;
+        if (er) er[i] = e;
+        if (++x == W) { x = 0; ++y; }
+    }
+}
+
 // ----------------------------------------------------- sparsification --
 // Sec. 3.1 (minimum matches s from Table 3): the level-0 image is cut into
 // 3x3 blocks from the origin, partial at the right and bottom borders.  One
@@ -1400,6 +1446,14 @@ void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, i
 void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fb, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
+}
+void launch_save_state(const PairDev* d, int npairs, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_save_state, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
+}
+void launch_fb2(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fb2, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
 }
 void launch_sparse(const PairDev* d, int npairs, int eps2, int s, int maxW, int maxH, hipStream_t st)
 {

@@ -37,6 +37,8 @@ bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
 void launch_sparse(const PairDev*, int, int, int, int, int, hipStream_t);
+void launch_save_state(const PairDev*, int, int, hipStream_t);
+void launch_fb2(const PairDev*, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
 }  // namespace ff
@@ -167,6 +169,7 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
     b += 2 * align_up((size_t)pl.W[c] * pl.H[c] * 64);
     b += 2 * align_up((size_t)pl.nsx * pl.nsy * 8);
     if (p.flags & FF_SPARSIFY) b += 2 * align_up((size_t)W * H * 4);   // consistency errors
+    if (p.flags & FF_SECOND_CHECK) b += 2 * align_up((size_t)W * H * 8);   // first search's level-0 state
     pl.bytes = b;
     return pl;
 }
@@ -178,7 +181,7 @@ ff_status validate_params(ff_ctx* h, const ff_params& p)
     if (p.iters < 0 || p.iters > 64) return fail(h, FF_ERR_INVALID, "iters must be in 0..64");
     if (p.rs_radius < 0 || p.rs_radius > 1024) return fail(h, FF_ERR_INVALID, "rs_radius must be in 0..1024");
     if (p.fb_eps < 0 || p.fb_eps > 1024) return fail(h, FF_ERR_INVALID, "fb_eps must be in 0..1024");
-    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS)) return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK)) return fail(h, FF_ERR_INVALID, "unknown flag bits");
     if ((p.flags & FF_SPARSIFY) && (p.sparse_min < 1 || p.sparse_min > 9))
         return fail(h, FF_ERR_INVALID, "sparse_min must be in 1..9");
     return FF_OK;
@@ -287,6 +290,8 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
         d.fberr[1] = pairs[i].fberr_bwd;
         d.sparse[0] = pairs[i].sparse_fwd;
         d.sparse[1] = pairs[i].sparse_bwd;
+        if (p.flags & FF_SECOND_CHECK)
+            for (int k = 0; k < 2; ++k) d.save[k] = (int2*)take((size_t)pl.W[0] * pl.H[0] * 8);
         if (p.flags & FF_SPARSIFY) {
             const size_t np = (size_t)pl.W[0] * pl.H[0];
             for (int k = 0; k < 2; ++k) {
@@ -350,10 +355,10 @@ SearchConst search_const(const ff_params& p)
     return sc;
 }
 
-const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn",
-                                    "init", "row_phase", "col_phase", "transpose", "fb", "sparse", "census"};
+const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn", "init", "row_phase",
+                                    "col_phase", "transpose", "fb", "sparse", "census", "save_state"};
 enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_SPARSE,
-       KN_CENSUS, KN_COUNT };
+       KN_CENSUS, KN_SAVE, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
@@ -437,35 +442,48 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         launch_keys_to_index(tab0->keys[stop.st.dir], (int32_t*)stop.dst, plan0->nsx * plan0->nsy, st);
         return FF_OK;
     }
-    for (int l = c; l >= 0; --l) {
-        FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
-        const bool stop_here = stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
-        if (stop_here && stop.st.step == 0) {
-            FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
-            return FF_OK;
-        }
-        for (int t = 0; t < p.iters; ++t) {
-            const bool last = stop_here && stop.st.iter == t;
-            const int upto = last ? stop.st.step : 7;
-            FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census, d, n, l, t,
-                                                std::min(upto, 3), sc, D.maxH[l], D.maxW[l], st));
-            if (upto >= 4) {
-                // the column phase reads the row-major state; its result comes
-                // back row-major when the cross write applies, else from stateT
-                FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census, d, n, l, t, upto, sc,
-                                                    D.maxW[l], D.maxH[l], st));
-                if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
-                    FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
-            }
-            if (last) {
-                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8,
-                                         hipMemcpyDeviceToDevice, st));
+    // The search; with FF_SECOND_CHECK it runs again keyed by seed2 after
+    // the first search's level-0 state is saved (debug stops name the first).
+    const bool second = (p.flags & FF_SECOND_CHECK) != 0;
+    SearchConst sc2 = sc;
+    sc2.key0 = (uint32_t)p.seed2;
+    sc2.key1 = (uint32_t)(p.seed2 >> 32);
+    for (int run_k = 0; run_k < (second ? 2 : 1); ++run_k) {
+        const SearchConst& scr = run_k ? sc2 : sc;
+        if (run_k == 1) FF_TRACED(KN_SAVE, 0, launch_save_state(d, n, D.maxPx[0], st));
+        for (int l = c; l >= 0; --l) {
+            FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
+            const bool stop_here = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
+            if (stop_here && stop.st.step == 0) {
+                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
                 return FF_OK;
+            }
+            for (int t = 0; t < p.iters; ++t) {
+                const bool last = stop_here && stop.st.iter == t;
+                const int upto = last ? stop.st.step : 7;
+                FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census, d, n, l, t,
+                                                    std::min(upto, 3), scr, D.maxH[l], D.maxW[l], st));
+                if (upto >= 4) {
+                    // the column phase reads the row-major state; its result comes
+                    // back row-major when the cross write applies, else from stateT
+                    FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census, d, n, l, t, upto, scr,
+                                                        D.maxW[l], D.maxH[l], st));
+                    if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
+                        FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
+                }
+                if (last) {
+                    FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8,
+                                             hipMemcpyDeviceToDevice, st));
+                    return FF_OK;
+                }
             }
         }
     }
     if (stop.active) return fail(h, FF_ERR_INVALID, "debug stage names a point the schedule does not reach");
-    FF_TRACED(KN_FB, 0, launch_fb(d, n, sc.eps2, D.maxPx[0], st));
+    if (second)
+        FF_TRACED(KN_FB, 0, launch_fb2(d, n, sc.eps2, D.maxPx[0], st));
+    else
+        FF_TRACED(KN_FB, 0, launch_fb(d, n, sc.eps2, D.maxPx[0], st));
     if (p.flags & FF_SPARSIFY)
         FF_TRACED(KN_SPARSE, 0, launch_sparse(d, n, sc.eps2, p.sparse_min, D.maxW[0], D.maxH[0], st));
     return FF_OK;

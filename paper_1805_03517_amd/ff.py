@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libff.so")
 FF_OK, FF_ERR_INVALID, FF_ERR_OOM, FF_ERR_BUDGET, FF_ERR_HIP, FF_ERR_UNSUPPORTED, FF_ERR_BUSY = range(7)
 FF_SPARSIFY = 1                                  # params.flags: 3x3-block sparsification
 FF_COST_CENSUS = 2                               # params.flags: 7x7 Census (Hamming) matching cost
+FF_SECOND_CHECK = 4                              # params.flags: second consistency check (search keyed by seed2)
 STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE, STAGE_CENSUS = range(6)
 INF = 2**31 - 1
 
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
                 ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("sparse_min", ctypes.c_int32)]
+                ("sparse_min", ctypes.c_int32), ("seed2", ctypes.c_uint64)]
 
 
 class Pair(ctypes.Structure):
@@ -116,20 +117,23 @@ class Matcher:
     [H, W] (gray) or [H, W, 3] (RGB), contiguous."""
 
     def __init__(self, levels=4, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
-                 hbm_budget=0, device=0, sparse_min=0, cost="wh"):
+                 hbm_budget=0, device=0, sparse_min=0, cost="wh", seed2=None):
         """sparse_min > 0 turns on the 3x3-block sparsification (FF_SPARSIFY)
         with that minimum number of matches s; outputs then include
         sparse_f / sparse_b and the consistency errors fberr_f / fberr_b.
         cost: "wh" (descriptor SAD) or "census" (7x7 Census Hamming distance,
-        FF_COST_CENSUS)."""
+        FF_COST_CENSUS).  seed2 (not None) adds the second consistency check
+        against the inverse fields of a search keyed by seed2 (FF_SECOND_CHECK)."""
         if cost not in ("wh", "census"):
             raise FFError(FF_ERR_INVALID, "cost must be 'wh' or 'census'")
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
         self.sparse = sparse_min > 0
-        flags = (FF_SPARSIFY if self.sparse else 0) | (FF_COST_CENSUS if cost == "census" else 0)
-        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget, flags, sparse_min)
+        flags = ((FF_SPARSIFY if self.sparse else 0) | (FF_COST_CENSUS if cost == "census" else 0) |
+                 (FF_SECOND_CHECK if seed2 is not None else 0))
+        self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget, flags, sparse_min,
+                             seed2 if seed2 is not None else 0)
         h = ctypes.c_void_p()
         st = lib().ff_create(ctypes.byref(self.params), device, ctypes.byref(h))
         if st != FF_OK:
