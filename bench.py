@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time per-pair ff_match_pair calls")
     ap.add_argument("--autotune", action="store_true", help="re-tune the line-kernel schedule first")
-    ap.add_argument("--default-schedule", action="store_true", help="chunks 4, lines 4 everywhere")
+    ap.add_argument("--default-schedule", action="store_true", help="the handle's default schedule")
     ap.add_argument("--seednn-only", action="store_true",
                     help="only time the seed search at the large shape (for counter runs)")
     ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")

@@ -178,8 +178,8 @@ int32_t   ff_serve_inflight(ff_handle h);
  * writes 6 * levels int32 (cfg[(phase * levels + level) * 3 + {0: chunks,
  * 1: lines, 2: staged}], phase 0 = row, 1 = column) and returns that count,
  * or -1 if max is too small; ff_tune_set installs such a vector
- * (FF_ERR_INVALID for an unsupported triple).  The default is (4, 4, 0)
- * everywhere.                                                             */
+ * (FF_ERR_INVALID for an unsupported triple).  The default is (1, 4, 0) for
+ * the row phase and (1, 8, 0) for the column phase at every level.        */
 ff_status ff_autotune(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
 int32_t   ff_tune_get(ff_handle h, int32_t* cfg, int32_t max);
 ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n);

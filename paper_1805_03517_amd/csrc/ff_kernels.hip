@@ -643,6 +643,24 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 // Finer levels: twice the flow of the parent pixel (clamped to the coarse
 // grid).  Cost re-evaluated on the descriptors or, with census set, on the
 // Census strings.  grid (pixels / 256, 2 * pairs).
+// Init flow of pixel (x, y) at `level`: the seed of its stride cell at the
+// coarsest level, else twice the final flow of its parent (clamped to the
+// coarse grid).
+__device__ __forceinline__ uint32_t init_flow(const PairDev& P, int dir, int level, bool coarsest, int stride, int W,
+                                              int x, int y)
+{
+    if (coarsest) {
+        const int si = x / stride, sj = y / stride;
+        const unsigned long long key = P.keys[dir][sj * P.nsx + si];
+        const uint32_t q = 0xFFFFFFFFu - (uint32_t)key;
+        return pack_flow((int)(q % (uint32_t)W) - si * stride, (int)(q / (uint32_t)W) - sj * stride);
+    }
+    const LevelDev& C = P.lv[level + 1];
+    const int cx = min(x >> 1, C.W - 1), cy = min(y >> 1, C.H - 1);
+    const uint32_t cf = (uint32_t)((const gi2*)C.state[dir])[(uint32_t)cy * (uint32_t)C.W + (uint32_t)cx].x;
+    return pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
+}
+
 __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs, int level, int coarsest,
                                               int stride, int census)
 {
@@ -653,18 +671,7 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= W * H) return;
     const int x = i % W, y = i / W;
-    uint32_t f;
-    if (coarsest) {
-        const int si = x / stride, sj = y / stride;
-        const unsigned long long key = P.keys[dir][sj * P.nsx + si];
-        const uint32_t q = 0xFFFFFFFFu - (uint32_t)key;
-        f = pack_flow((int)(q % (uint32_t)W) - si * stride, (int)(q / (uint32_t)W) - sj * stride);
-    } else {
-        const LevelDev& C = P.lv[level + 1];
-        const int cx = min(x >> 1, C.W - 1), cy = min(y >> 1, C.H - 1);
-        const uint32_t cf = (uint32_t)C.state[dir][(size_t)cy * C.W + cx].x;
-        f = pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
-    }
+    const uint32_t f = init_flow(P, dir, level, coarsest != 0, stride, W, x, y);
     const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
                              : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
     L.state[dir][i] = make_int2((int)f, c);
@@ -726,7 +733,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                                                     bool lin, bool lout, li2* lline, int W, int H, int len, int line,
                                                     int lane,
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
-                                                    const SearchConst& sc)
+                                                    const SearchConst& sc, const PairDev& P, int dir, int initc)
 {
     using FT = typename Feat<CK>::T;
     constexpr int WIN = 64 * CH;
@@ -742,8 +749,16 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
         for (int c = 0; c < CH; ++c) {
             const int p = w0 + 64 * c + lane;
             const bool valid = p < len;
-            const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
             A[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
+            i32x2 st = i32x2{0, kInf};
+            if (valid) {
+                if (initc) {                                     // row phase, first pass of iteration 0
+                    const uint32_t f = init_flow(P, dir, (int)level, initc == 2, sc.stride, W, p, line);
+                    st = i32x2{(int)f, feat_cost<false, CK>(DB, W, H, p, line, f, A[c])};
+                } else {
+                    st = lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
+                }
+            }
             F[c] = (uint32_t)st.x;
             C[c] = st.y;
         }
@@ -896,7 +911,7 @@ struct StageDims {
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
-                                                         int iter, int upto, SearchConst sc, int xw)
+                                                         int iter, int upto, SearchConst sc, int xw, int finit)
 {
     static_assert(!STG || CK == 0, "the staged random search holds descriptors");
     using FT = typename Feat<CK>::T;
@@ -973,7 +988,8 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         if constexpr (!STG && RC > 0 && CH <= 2) {
             if (active)
                 line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
-                                                 (uint32_t)level, ctr2, sc);
+                                                 (uint32_t)level, ctr2, sc, P, dir,
+                                                 (!COL && fwd && finit) ? (level == sc.levels - 1 ? 2 : 1) : 0);
             continue;
         }
         uint32_t carry = 0;
@@ -1383,21 +1399,21 @@ bool line_cross_write(int wpb, int maxlen)
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
-                   int maxlen, hipStream_t st)
+                   int maxlen, int finit, hipStream_t st)
 {
     const int xw = line_cross_write(WPB, maxlen) ? 1 : 0;
     const size_t dyn = xw ? (size_t)WPB * maxlen * sizeof(int2) : 0;
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
-                       dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw);
+                       dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw, finit);
 }
 
 template <int RC, bool COL, int CK>
 bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
-                    const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
+                    const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
 #define FF_LINE_CASE(C, B, G)                                                                        \
     if (ch == C && wpb == B && stg == G) {                                                           \
-        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, st); \
+        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st); \
         return true;                                                                                 \
     }
     FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
@@ -1413,13 +1429,14 @@ bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int 
 
 template <int CK>
 bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
-                    int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
+                    int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
     if (sc.radius == 16)
-        return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
-                   : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
-    return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
-               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+        return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+                   : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit,
+                                                   st);
+    return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
 }
 
 // One row or column phase of every pair and direction at one level.  ch =
@@ -1431,11 +1448,21 @@ bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int np
 // nlines / maxlen: the batch's largest line count and line length.  The
 // column phase reads the row-major state and, when line_cross_write()
 // allows it, also writes it (otherwise its result stays in stateT).
+// finit: the row phase of iteration 0 computes the level init itself (the
+// first pass loads each pixel's init flow and costs it instead of reading a
+// state written by k_init); only the software-pipelined pass supports it --
+// see line_fused_init().
 bool launch_line_phase(bool col, int ch, int wpb, int stg, bool census, const PairDev* d, int npairs, int level,
-                       int iter, int upto, const SearchConst& sc, int nlines, int maxlen, hipStream_t st)
+                       int iter, int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
-    return census ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st)
-                  : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, st);
+    return census ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st)
+                  : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
+}
+
+// Whether the row phase with this schedule can take over the level init.
+bool line_fused_init(int ch, int stg, const SearchConst& sc)
+{
+    return sc.radius == 16 && stg == 0 && ch <= 2;
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

@@ -32,7 +32,8 @@ void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, int, hipStream_t);
 void launch_census(const PairDev*, int, int, int, int, hipStream_t);
 bool launch_line_phase(bool, int, int, int, bool, const PairDev*, int, int, int, int, const SearchConst&, int, int,
-                       hipStream_t);
+                       int, hipStream_t);
+bool line_fused_init(int ch, int stg, const SearchConst& sc);
 bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_fb(const PairDev*, int, int, int, hipStream_t);
@@ -85,8 +86,8 @@ struct ff_ctx {
     // line-kernel schedule per phase (0 row, 1 col) and level: chunks of 64 px
     // per relaxation window, lines per block and LDS staging of the random
     // search (set by ff_autotune / ff_tune_set)
-    int tune_ch[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
-    int tune_wpb[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {4, 4, 4, 4, 4, 4, 4, 4}};
+    int tune_ch[2][kMaxLevels] = {{1, 1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1, 1}};
+    int tune_wpb[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {8, 8, 8, 8, 8, 8, 8, 8}};
     int tune_stg[2][kMaxLevels] = {};          // 1 = random search reads a staged LDS neighbourhood
 };
 
@@ -452,8 +453,13 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         const SearchConst& scr = run_k ? sc2 : sc;
         if (run_k == 1) FF_TRACED(KN_SAVE, 0, launch_save_state(d, n, D.maxPx[0], st));
         for (int l = c; l >= 0; --l) {
-            FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
             const bool stop_here = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
+            // the row phase of iteration 0 takes over the init when its
+            // schedule allows (and no stop asks for the init state itself)
+            const bool fuse = p.iters > 0 && line_fused_init(h->tune_ch[0][l], h->tune_stg[0][l], scr) &&
+                              !(stop_here && stop.st.step == 0);
+            if (!fuse)
+                FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
             if (stop_here && stop.st.step == 0) {
                 FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
                 return FF_OK;
@@ -462,12 +468,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                 const bool last = stop_here && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
                 FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census, d, n, l, t,
-                                                    std::min(upto, 3), scr, D.maxH[l], D.maxW[l], st));
+                                                    std::min(upto, 3), scr, D.maxH[l], D.maxW[l], fuse && t == 0, st));
                 if (upto >= 4) {
                     // the column phase reads the row-major state; its result comes
                     // back row-major when the cross write applies, else from stateT
                     FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census, d, n, l, t, upto, scr,
-                                                        D.maxW[l], D.maxH[l], st));
+                                                        D.maxW[l], D.maxH[l], 0, st));
                     if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
                         FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
                 }

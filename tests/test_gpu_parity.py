@@ -67,7 +67,11 @@ def _run_pair(torch, ffm, orc, i1, i2, p, tag, schedule=None):
 
 
 # ------------------------------------------------------ stage parity ----
-def test_stage_parity_config0(torch, ffm, orc):
+@pytest.mark.parametrize("schedule", ["default", "generic"])
+def test_stage_parity_config0(torch, ffm, orc, schedule):
+    """Every intermediate against the oracle: with the default schedule
+    (software-pipelined pass; the row phase takes over the level init) and
+    with the generic windowed pass (separate init kernel)."""
     i1, i2, _ = synth.config0()
     p = _prm(orc, levels=3)
     trace = {}
@@ -76,6 +80,8 @@ def test_stage_parity_config0(torch, ffm, orc):
         trace[(d, l, t, s)] = (f, c)
     orc.match(i1, i2, p, trace=tr)
     m = _matcher(ffm, p)
+    if schedule == "generic":
+        m.set_tuning([4, 4, 0] * 6)
     a, b = _dev(torch, i1), _dev(torch, i2)
     grays = [orc.gray(i1), orc.gray(i2)]
     pyrs = [orc.pyramid(g, 3) for g in grays]
@@ -163,7 +169,7 @@ def _staged_schedule(levels):
     return list(STAGED["row"]) * levels + list(STAGED["col"]) * levels
 
 
-@pytest.mark.parametrize("staged", [False, True, "pipelined"], ids=["direct", "staged", "pipelined"])
+@pytest.mark.parametrize("staged", [False, True, "pipelined"], ids=["generic", "staged", "pipelined"])
 @pytest.mark.parametrize("case", EDGE_CASES, ids=[f"{c[0]}x{c[1]}c{c[2]}L{c[3]}s{c[4]}R{c[5]}e{c[6]}T{c[7]}"
                                                   for c in EDGE_CASES])
 def test_edge_shapes(torch, ffm, orc, case, staged):
@@ -177,7 +183,7 @@ def test_edge_shapes(torch, ffm, orc, case, staged):
         i1 = np.stack([c[0] for c in chans], -1)
         i2 = np.stack([c[1] for c in chans], -1)
     p = _prm(orc, levels=L, seed_stride=st, iters=T, rs_radius=R, fb_eps=eps)
-    sched = None
+    sched = [4, 4, 0] * L + [4, 4, 0] * L                  # generic windowed pass
     if staged == "pipelined":
         sched = [1, 8, 0] * L + [2, 4, 0] * L
     elif staged:
