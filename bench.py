@@ -60,6 +60,35 @@ def level_dims(w, h, levels):
 #   col phase: TB (1) + RS (5) + BT (1) + RS (5)          = 12 gathers
 ROW_BYTES_PER_PX = 7 * 16 + 32
 COL_BYTES_PER_PX = 12 * 16 + 32
+INIT_BYTES_PER_PX = 8 + 16 + 16 + 8     # coarse state, own descriptor, candidate, state write
+
+
+def kernel_rooflines(prof, batch, steps):
+    """Every kernel of the step against HBM (algorithmic bytes per step /
+    its device time per step): what each step of the method must move, every
+    candidate gather counted, no cache reuse.  The level init runs inside the
+    row phase's first pass of iteration 0, so its bytes are charged there."""
+    dims = level_dims(W0, H0, LEVELS)
+    px = [w * h for w, h in dims]
+    p0, pall, pc = px[0], sum(px), px[-1]
+    per_step = {
+        "gray": 4 * p0 * 2 * batch,                               # 3 B RGB in, 1 B luma out, 2 images
+        "down2": sum(5 * q for q in px[1:]) * 2 * batch,          # 4 B in, 1 B out per output pixel
+        "desc": 33 * pall * 2 * batch,                            # 1 B luma in, 2 x 16 B out
+        "seed_records": 80 * pc * 2 * batch,                      # 16 B in, 64 B record out
+        "row_phase": (2 * ROW_BYTES_PER_PX + INIT_BYTES_PER_PX) * pall * 2 * batch,
+        "col_phase": 2 * COL_BYTES_PER_PX * pall * 2 * batch,
+        "fb": 25 * p0 * 2 * batch,                                # own 8 + other 8 in, 4 + 4 + 1 out
+    }
+    out = {}
+    for k, b in per_step.items():
+        if k not in prof:
+            continue
+        sec = prof[k][1] / 1000.0 / steps
+        gbs = b / sec / 1e9
+        out[k] = {"bytes_per_step": b, "us_per_step": sec * 1e6, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def make_inputs(torch, batch, distinct):
@@ -512,6 +541,7 @@ def main():
                                  if TRAFFIC["kernel_sha"] == kernel_sha() and tuning == SCHEDULE_C1 else None),
                      "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": avg_bytes},
         "kernels": kernels,
+        "kernel_rooflines": kernel_rooflines(prof, args.batch, args.steps),
         "plain": plain,
         "seed_nn": seednn,
         "sparsify": sparse,
