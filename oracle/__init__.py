@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("seed_stride", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
                 ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("cost_kind", ctypes.c_int32),
-                ("two_checks", ctypes.c_int32), ("seed2", ctypes.c_uint64)]
+                ("two_checks", ctypes.c_int32), ("seed2", ctypes.c_uint64),
+                ("sub_iters", ctypes.c_int32), ("sub_radius", ctypes.c_int32)]
 
 
 COST_WH, COST_CENSUS = 0, 1
@@ -65,6 +66,12 @@ def lib():
         l.ffo_fb_error.argtypes = [i, i, P, P, P, P, P]
         l.ffo_sparsify.argtypes = [i, i, P, P, i, P]
         l.ffo_fb_error2.argtypes = [i, i, P, P, P, P, P, P, P]
+        l.ffo_fb_error_u.argtypes = [i, i, i, P, P, P, P, P]
+        l.ffo_fb_error2_u.argtypes = [i, i, i, P, P, P, P, P, P, P]
+        l.ffo_cost_subpix.argtypes = [P, P, i, i, i, i, i, i]
+        l.ffo_cost_subpix.restype = ctypes.c_int32
+        l.ffo_sweep_subpix.argtypes = [P, P, i, i, i, P, P]
+        l.ffo_random_search_subpix.argtypes = [P, P, i, i, i, i, i, i, ctypes.c_uint64, P, P]
         l.ffo_census.argtypes = [P, i, i, P]
         l.ffo_cost_census.argtypes = [P, P, i, i, i, i, i, i]
         l.ffo_cost_census.restype = ctypes.c_int32
@@ -88,8 +95,9 @@ def _p(a: np.ndarray):
 
 
 def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, cost_kind=COST_WH,
-           two_checks=0, seed2=0) -> Params:
-    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind, two_checks, seed2)
+           two_checks=0, seed2=0, sub_iters=0, sub_radius=2) -> Params:
+    return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind, two_checks, seed2,
+                  sub_iters, sub_radius)
 
 
 def gray(img: np.ndarray) -> np.ndarray:
@@ -216,27 +224,62 @@ def random_search_census(CA, CB, flow, cst, level, it, pss, radius, seed):
     return f, c
 
 
-def fb_error(F, cF, B, cB) -> np.ndarray:
+def fb_error(F, cF, B, cB, unit: int = 1) -> np.ndarray:
     """Sec. 3.1 consistency error per pixel: |F(p) + B(p + F(p))|^2, INF
-    where either match is invalid."""
+    where either match is invalid; flows in 1/unit pixels (q rounded)."""
     F = np.ascontiguousarray(F, dtype=np.int16)
     B = np.ascontiguousarray(B, dtype=np.int16)
     cF = np.ascontiguousarray(cF, dtype=np.int32)
     cB = np.ascontiguousarray(cB, dtype=np.int32)
     H, W = cF.shape
     out = np.empty((H, W), np.int32)
-    lib().ffo_fb_error(W, H, _p(F), _p(cF), _p(B), _p(cB), _p(out))
+    if unit == 1:
+        lib().ffo_fb_error(W, H, _p(F), _p(cF), _p(B), _p(cB), _p(out))
+    else:
+        lib().ffo_fb_error_u(W, H, unit, _p(F), _p(cF), _p(B), _p(cB), _p(out))
     return out
 
 
-def fb_error2(F, cF, B1, cB1, B2, cB2) -> np.ndarray:
+def cost_subpix(DA, DB, x, y, u, v) -> int:
+    """Sec. 3.1 sub-pixel cost, (u, v) in quarter pixels."""
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    return int(lib().ffo_cost_subpix(_p(DA), _p(DB), W, H, x, y, u, v))
+
+
+def sweep_subpix(DA, DB, flow, cst, dir_code: int):
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_sweep_subpix(_p(DA), _p(DB), W, H, dir_code, _p(f), _p(c))
+    return f, c
+
+
+def random_search_subpix(DA, DB, flow, cst, level, it, pss, radius, seed):
+    DA = np.ascontiguousarray(DA, dtype=np.int8)
+    DB = np.ascontiguousarray(DB, dtype=np.int8)
+    H, W = DA.shape[:2]
+    f = np.array(flow, dtype=np.int16, copy=True, order="C")
+    c = np.array(cst, dtype=np.int32, copy=True, order="C")
+    lib().ffo_random_search_subpix(_p(DA), _p(DB), W, H, level, it, pss, radius,
+                                   ctypes.c_uint64(seed), _p(f), _p(c))
+    return f, c
+
+
+def fb_error2(F, cF, B1, cB1, B2, cB2, unit: int = 1) -> np.ndarray:
     """Sec. 3.1 two consistency checks: the larger of the errors against the
     inverse fields B1 and B2 (INF when either is)."""
     a = [np.ascontiguousarray(v, dtype=np.int16) for v in (F, B1, B2)]
     c = [np.ascontiguousarray(v, dtype=np.int32) for v in (cF, cB1, cB2)]
     H, W = c[0].shape
     out = np.empty((H, W), np.int32)
-    lib().ffo_fb_error2(W, H, _p(a[0]), _p(c[0]), _p(a[1]), _p(c[1]), _p(a[2]), _p(c[2]), _p(out))
+    if unit == 1:
+        lib().ffo_fb_error2(W, H, _p(a[0]), _p(c[0]), _p(a[1]), _p(c[1]), _p(a[2]), _p(c[2]), _p(out))
+    else:
+        lib().ffo_fb_error2_u(W, H, unit, _p(a[0]), _p(c[0]), _p(a[1]), _p(c[1]), _p(a[2]), _p(c[2]), _p(out))
     return out
 
 

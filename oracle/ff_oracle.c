@@ -77,6 +77,7 @@ static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v
 /* Floor division by 64 for any sign (the arithmetic shift the quantiser
  * reading uses), written without relying on >> of negative numbers.      */
 static int floor_div64(int v) { return v >= 0 ? v / 64 : -((-v + 63) / 64); }
+static int floor_div(int v, int d) { return v >= 0 ? v / d : -((-v + d - 1) / d); }
 
 void ffo_descriptors(const uint8_t* P, int W, int H, int8_t* D)
 {
@@ -154,8 +155,36 @@ int32_t ffo_cost_census(const uint64_t* CA, const uint64_t* CB, int W, int H, in
     return n;
 }
 
-/* A level's matching-cost plane of one image: the descriptors (SAD) or the
- * Census strings (Hamming), as params.cost_kind selects.                    */
+/* ---------------------------------------------------------- sub-pixel --- */
+/* Sub-pixel matching (Sec. 3.1: sub-pixel locations are interpolated
+ * bilinearly).  Reading: a refinement at level 0 on flows in quarter pixels;
+ * the cost of a quarter-pixel target interpolates B's biased descriptor
+ * bytes with integer bilinear weights and rounds half up, then takes the
+ * SAD.  The 2x2 neighbour with zero weight is not read.                    */
+int32_t ffo_cost_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int x, int y, int u, int v)
+{
+    int tx = 4 * x + u, ty = 4 * y + v;
+    if (tx < 0 || ty < 0) return FFO_INF;
+    int ix = tx / 4, iy = ty / 4, ax = tx % 4, ay = ty % 4;
+    if (ix > W - 1 || iy > H - 1 || (ix == W - 1 && ax != 0) || (iy == H - 1 && ay != 0)) return FFO_INF;
+    int ix1 = ax ? ix + 1 : ix, iy1 = ay ? iy + 1 : iy;
+    const int8_t* a = DA + ((size_t)y * W + x) * FFO_K;
+    const int8_t* b00 = DB + ((size_t)iy * W + ix) * FFO_K;
+    const int8_t* b10 = DB + ((size_t)iy * W + ix1) * FFO_K;
+    const int8_t* b01 = DB + ((size_t)iy1 * W + ix) * FFO_K;
+    const int8_t* b11 = DB + ((size_t)iy1 * W + ix1) * FFO_K;
+    int w00 = (4 - ax) * (4 - ay), w10 = ax * (4 - ay), w01 = (4 - ax) * ay, w11 = ax * ay;
+    int32_t s = 0;
+    for (int k = 0; k < FFO_K; ++k) {
+        int i = (w00 * (b00[k] + 128) + w10 * (b10[k] + 128) + w01 * (b01[k] + 128) + w11 * (b11[k] + 128) + 8) >> 4;
+        s += abs(a[k] + 128 - i);
+    }
+    return s;
+}
+
+/* A level's matching-cost plane of one image: the descriptors (SAD, or the
+ * sub-pixel SAD on quarter-pixel flows) or the Census strings (Hamming), as
+ * params.cost_kind selects.                                                 */
 typedef struct {
     int kind;
     const int8_t* desc;
@@ -165,6 +194,7 @@ typedef struct {
 static int32_t plane_cost(const cplane* A, const cplane* B, int W, int H, int x, int y, int fx, int fy)
 {
     if (A->kind == FFO_COST_CENSUS) return ffo_cost_census(A->cen, B->cen, W, H, x, y, fx, fy);
+    if (A->kind == FFO_COST_SUBPIX) return ffo_cost_subpix(A->desc, B->desc, W, H, x, y, fx, fy);
     return ffo_cost(A->desc, B->desc, W, H, x, y, fx, fy);
 }
 
@@ -344,6 +374,19 @@ void ffo_random_search_census(const uint64_t* CA, const uint64_t* CB, int W, int
     random_search_planes(&A, &B, W, H, level, iter, pass, radius, seed, flow, cost);
 }
 
+void ffo_sweep_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code, int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_SUBPIX, DA, NULL}, B = {FFO_COST_SUBPIX, DB, NULL};
+    sweep_planes(&A, &B, W, H, dir_code, flow, cost);
+}
+
+void ffo_random_search_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int level, int iter, int pass,
+                              int radius, uint64_t seed, int16_t* flow, int32_t* cost)
+{
+    cplane A = {FFO_COST_SUBPIX, DA, NULL}, B = {FFO_COST_SUBPIX, DB, NULL};
+    random_search_planes(&A, &B, W, H, level, iter, pass, radius, seed, flow, cost);
+}
+
 /* --------------------------------------------------------- full search -- */
 typedef struct {
     int W, H;
@@ -430,6 +473,35 @@ static void search_direction(const ffo_params* p, const level_t* lv, int ia, int
             trace_call(trace, user, dir, l, t, 7, W, H, flow, cost);
         }
     }
+    if (p->sub_iters > 0) {
+        /* Sub-pixel refinement at level 0 (Sec. 3.1): flows to quarter
+         * pixels (costs unchanged: zero fraction), then sub_iters times the
+         * same schedule with the interpolated cost; random search radius in
+         * quarter pixels, Philox level index = number of pyramid levels.  */
+        int W = lv[0].W, H = lv[0].H;
+        for (size_t q = 0; q < (size_t)W * H; ++q) {
+            flow[2 * q] = (int16_t)(4 * flow[2 * q]);
+            flow[2 * q + 1] = (int16_t)(4 * flow[2 * q + 1]);
+        }
+        const cplane A = {FFO_COST_SUBPIX, lv[0].desc[ia], NULL}, B = {FFO_COST_SUBPIX, lv[0].desc[ib], NULL};
+        trace_call(trace, user, dir, L, -1, 0, W, H, flow, cost);
+        for (int t = 0; t < p->sub_iters; ++t) {
+            sweep_planes(&A, &B, W, H, 0, flow, cost);
+            trace_call(trace, user, dir, L, t, 1, W, H, flow, cost);
+            sweep_planes(&A, &B, W, H, 1, flow, cost);
+            trace_call(trace, user, dir, L, t, 2, W, H, flow, cost);
+            random_search_planes(&A, &B, W, H, L, t, 0, p->sub_radius, p->seed, flow, cost);
+            trace_call(trace, user, dir, L, t, 3, W, H, flow, cost);
+            sweep_planes(&A, &B, W, H, 2, flow, cost);
+            trace_call(trace, user, dir, L, t, 4, W, H, flow, cost);
+            random_search_planes(&A, &B, W, H, L, t, 1, p->sub_radius, p->seed, flow, cost);
+            trace_call(trace, user, dir, L, t, 5, W, H, flow, cost);
+            sweep_planes(&A, &B, W, H, 3, flow, cost);
+            trace_call(trace, user, dir, L, t, 6, W, H, flow, cost);
+            random_search_planes(&A, &B, W, H, L, t, 2, p->sub_radius, p->seed, flow, cost);
+            trace_call(trace, user, dir, L, t, 7, W, H, flow, cost);
+        }
+    }
 }
 
 /* Forward-backward consistency check (Sec. 3.1; threshold epsilon, Table 3):
@@ -454,16 +526,18 @@ static void consistency(int W, int H, int eps, const int16_t* F, const int32_t* 
         }
 }
 
-/* Consistency error (Sec. 3.1), the quantity the mask thresholds.       */
-void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
-                  const int16_t* B, const int32_t* cB, int32_t* err)
+/* Consistency error (Sec. 3.1), the quantity the mask thresholds, for
+ * flows in 1/unit pixels: q = p + F(p) rounded half up to whole pixels (an
+ * identity for unit 1), error |F(p) + B(q)|^2 in 1/unit^2 px^2.          */
+void ffo_fb_error_u(int W, int H, int unit, const int16_t* F, const int32_t* cF,
+                    const int16_t* B, const int32_t* cB, int32_t* err)
 {
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             size_t p = (size_t)y * W + x;
             int32_t e = FFO_INF;
             if (cF[p] != FFO_INF) {
-                int qx = x + F[2 * p], qy = y + F[2 * p + 1];
+                int qx = x + floor_div(F[2 * p] + unit / 2, unit), qy = y + floor_div(F[2 * p + 1] + unit / 2, unit);
                 size_t q = (size_t)qy * W + qx;
                 if (cB[q] != FFO_INF) {
                     int ex = F[2 * p] + B[2 * q], ey = F[2 * p + 1] + B[2 * q + 1];
@@ -474,16 +548,28 @@ void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
         }
 }
 
+void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
+                  const int16_t* B, const int32_t* cB, int32_t* err)
+{
+    ffo_fb_error_u(W, H, 1, F, cF, B, cB, err);
+}
+
 /* Two consistency checks (Sec. 3.1): the larger of the two errors.       */
-void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,
-                   const int16_t* B2, const int32_t* cB2, int32_t* err)
+void ffo_fb_error2_u(int W, int H, int unit, const int16_t* F, const int32_t* cF, const int16_t* B1,
+                     const int32_t* cB1, const int16_t* B2, const int32_t* cB2, int32_t* err)
 {
     int32_t* e2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)W * H);
-    ffo_fb_error(W, H, F, cF, B1, cB1, err);
-    ffo_fb_error(W, H, F, cF, B2, cB2, e2);
+    ffo_fb_error_u(W, H, unit, F, cF, B1, cB1, err);
+    ffo_fb_error_u(W, H, unit, F, cF, B2, cB2, e2);
     for (size_t p = 0; p < (size_t)W * H; ++p)
         if (e2[p] > err[p]) err[p] = e2[p];
     free(e2);
+}
+
+void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,
+                   const int16_t* B2, const int32_t* cB2, int32_t* err)
+{
+    ffo_fb_error2_u(W, H, 1, F, cF, B1, cB1, B2, cB2, err);
 }
 
 /* Sparsification (Sec. 3.1, s from Table 3): one kept match per 3x3 block
@@ -523,6 +609,8 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
     if (p->levels < 1 || p->levels > 16 || p->seed_stride < 1 || p->iters < 0 ||
         p->rs_radius < 0 || p->fb_eps < 0 || (p->cost_kind != FFO_COST_WH && p->cost_kind != FFO_COST_CENSUS))
         return -1;
+    if (p->sub_iters < 0 || (p->sub_iters > 0 && (p->cost_kind != FFO_COST_WH || p->sub_radius < 0 || W > 2048 || H > 2048)))
+        return -1;
     if (W < 1 || H < 1 || (W >> (p->levels - 1)) < 1 || (H >> (p->levels - 1)) < 1) return -1;
 
     int L = p->levels;
@@ -557,9 +645,20 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
     search_direction(p, lv, 0, 1, 0, flow_f, cf, trace, user);
     search_direction(p, lv, 1, 0, 1, fb, cb, trace, user);
 
-    if (!p->two_checks) {
+    const int unit = p->sub_iters > 0 ? 4 : 1;          /* flows in quarter pixels after refinement */
+    const int eps2 = p->fb_eps * p->fb_eps * unit * unit;
+    if (!p->two_checks && unit == 1) {
         consistency(W, H, p->fb_eps, flow_f, cf, fb, cb, mask_f);
         if (mask_b) consistency(W, H, p->fb_eps, fb, cb, flow_f, cf, mask_b);
+    } else if (!p->two_checks) {
+        int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (size_t)W * H);
+        ffo_fb_error_u(W, H, unit, flow_f, cf, fb, cb, e);
+        for (size_t q = 0; q < (size_t)W * H; ++q) mask_f[q] = e[q] <= eps2 ? 1 : 0;
+        if (mask_b) {
+            ffo_fb_error_u(W, H, unit, fb, cb, flow_f, cf, e);
+            for (size_t q = 0; q < (size_t)W * H; ++q) mask_b[q] = e[q] <= eps2 ? 1 : 0;
+        }
+        free(e);
     } else {
         /* second pair of fields: the same search keyed by seed2; a match
          * must be consistent with both inverse fields (Sec. 3.1)          */
@@ -573,11 +672,10 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
         int32_t* e = (int32_t*)malloc(sizeof(int32_t) * n);
         search_direction(&p2, lv, 0, 1, 0, f2, cf2, NULL, NULL);
         search_direction(&p2, lv, 1, 0, 1, b2, cb2, NULL, NULL);
-        int eps2 = p->fb_eps * p->fb_eps;
-        ffo_fb_error2(W, H, flow_f, cf, fb, cb, b2, cb2, e);
+        ffo_fb_error2_u(W, H, unit, flow_f, cf, fb, cb, b2, cb2, e);
         for (size_t q = 0; q < n; ++q) mask_f[q] = e[q] <= eps2 ? 1 : 0;
         if (mask_b) {
-            ffo_fb_error2(W, H, fb, cb, flow_f, cf, f2, cf2, e);
+            ffo_fb_error2_u(W, H, unit, fb, cb, flow_f, cf, f2, cf2, e);
             for (size_t q = 0; q < n; ++q) mask_b[q] = e[q] <= eps2 ? 1 : 0;
         }
         free(f2); free(b2); free(cf2); free(cb2); free(e);

@@ -34,10 +34,16 @@ typedef struct {
     int32_t  two_checks;    /* 1: masks need a second check against the
                                inverse fields of a search keyed by seed2      */
     uint64_t seed2;         /* random-search key of the second search        */
+    int32_t  sub_iters;     /* > 0: sub-pixel refinement iterations at level 0
+                               (flows, errors and eps then in quarter pixels;
+                               descriptor cost only)                          */
+    int32_t  sub_radius;    /* its random-search radius in quarter pixels      */
 } ffo_params;
 
 #define FFO_COST_WH     0   /* SAD of the 16 Walsh-Hadamard coefficients     */
 #define FFO_COST_CENSUS 1   /* Hamming distance of 7x7 Census bit strings    */
+#define FFO_COST_SUBPIX 2   /* SAD against bilinearly interpolated descriptors,
+                               flows in quarter pixels (refinement only)      */
 
 /* Trace hook: called after every stage with the direction's state.
  * stage: 0 = level init, 1 = LR, 2 = RL, 3 = RS0, 4 = TB, 5 = RS1, 6 = BT,
@@ -64,6 +70,13 @@ int32_t ffo_nearest(const int8_t* a, const int8_t* DB, int N);
  * row-major order (dy outer, dx inner), is 1 when the neighbour is strictly
  * darker than the centre; border replicated.  out is [H][W].              */
 void ffo_census(const uint8_t* P, int W, int H, uint64_t* out);
+/* Sub-pixel cost (Sec. 3.1, bilinear interpolation): (u, v) in quarter
+ * pixels; the target (4x + u, 4y + v) must lie in [0, 4(W-1)] x [0, 4(H-1)];
+ * B's biased coefficients (d + 128) are interpolated from the 2x2
+ * neighbourhood with integer weights (4-ax)(4-ay), ax(4-ay), (4-ax)ay, ax ay
+ * (ax, ay = fraction in quarters), rounded half up ((sum + 8) >> 4); SAD
+ * against A's biased coefficients.  Zero fraction = the integer cost.     */
+int32_t ffo_cost_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int x, int y, int u, int v);
 /* Census matching cost: Hamming distance (0..48), INF outside image B.   */
 int32_t ffo_cost_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int x, int y, int fx, int fy);
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11).                        */
@@ -99,6 +112,10 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
  * FFO_INF otherwise.  The consistency mask is exactly err <= eps^2.       */
 void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
                   const int16_t* B, const int32_t* cB, int32_t* err);
+/* The same for flows in 1/unit pixels (unit 1 or 4): q = p + F(p) rounded
+ * half up to whole pixels, error in 1/unit^2 px^2.                         */
+void ffo_fb_error_u(int W, int H, int unit, const int16_t* F, const int32_t* cF,
+                    const int16_t* B, const int32_t* cB, int32_t* err);
 
 /* Two consistency checks (Sec. 3.1): F against two inverse fields B1 and B2
  * computed with different matching parameters.  err = the larger of the two
@@ -106,6 +123,13 @@ void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
  * err <= eps^2.                                                            */
 void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,
                    const int16_t* B2, const int32_t* cB2, int32_t* err);
+void ffo_fb_error2_u(int W, int H, int unit, const int16_t* F, const int32_t* cF, const int16_t* B1,
+                     const int32_t* cB1, const int16_t* B2, const int32_t* cB2, int32_t* err);
+/* The refinement's two steps on quarter-pixel flows (level index `level`
+ * in the Philox counter is the number of pyramid levels).                 */
+void ffo_sweep_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int dir_code, int16_t* flow, int32_t* cost);
+void ffo_random_search_subpix(const int8_t* DA, const int8_t* DB, int W, int H, int level, int iter, int pass,
+                              int radius, uint64_t seed, int16_t* flow, int32_t* cost);
 
 /* Sparsification (Sec. 3.1; minimum matches s from Table 3): the image is
  * cut into 3x3 blocks from the origin, the last column and row of blocks

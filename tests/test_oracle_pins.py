@@ -817,3 +817,105 @@ def test_census_end_to_end(orc):
     assert a["cost_f"][a["cost_f"] != orc.INF].max() <= 48
     w = orc.match(i1, i2, _prm(orc))
     assert not np.array_equal(w["cost_f"], a["cost_f"])        # the cost kind is honoured
+
+
+# ---------------------------------------------------------- sub-pixel cost --
+def test_subpix_cost_reduces_to_integer_cost(orc):
+    rng = np.random.default_rng(70)
+    DA = rng.integers(-128, 128, size=(9, 11, 16), dtype=np.int8)
+    DB = rng.integers(-128, 128, size=(9, 11, 16), dtype=np.int8)
+    for _ in range(300):
+        x, y = int(rng.integers(0, 11)), int(rng.integers(0, 9))
+        fx, fy = int(rng.integers(-13, 14)), int(rng.integers(-11, 12))
+        assert orc.cost_subpix(DA, DB, x, y, 4 * fx, 4 * fy) == orc.cost(DA, DB, x, y, fx, fy)
+
+
+def test_subpix_cost_worked_examples(orc):
+    # B: two pixels of constant coefficients d = 0 and d = 40 (biased 128, 168);
+    # A's pixel 0 holds d = 10 (biased 138)
+    DB = np.zeros((1, 2, 16), np.int8)
+    DB[0, 1] = 40
+    DA = np.full((1, 2, 16), 10, np.int8)
+    # quarter 1: (12*128 + 4*168 + 8) >> 4 = 138 -> 0; half: (8*128 + 8*168 + 8) >> 4 = 148 -> 10 per byte;
+    # three quarters: (4*128 + 12*168 + 8) >> 4 = 158 -> 20 per byte
+    assert orc.cost_subpix(DA, DB, 0, 0, 1, 0) == 0
+    assert orc.cost_subpix(DA, DB, 0, 0, 2, 0) == 160
+    assert orc.cost_subpix(DA, DB, 0, 0, 3, 0) == 320
+    assert orc.cost_subpix(DA, DB, 0, 0, 4, 0) == 16 * 30
+    # beyond the last column or before the first: INF; a zero-weight row past the edge is not needed
+    assert orc.cost_subpix(DA, DB, 0, 0, 5, 0) == orc.INF
+    assert orc.cost_subpix(DA, DB, 0, 0, -1, 0) == orc.INF
+    assert orc.cost_subpix(DA, DB, 0, 0, 1, 1) == orc.INF
+    # 2 x 2 with a diagonal fraction: weights (4-1)(4-2)=6, 1*2=2, 3*2=6, 1*2=2 over 0, 16, 32, 48
+    DB = np.zeros((2, 2, 16), np.int8)
+    DB[0, 1], DB[1, 0], DB[1, 1] = 16, 32, 48
+    DA = np.zeros((2, 2, 16), np.int8)
+    v = (6 * 128 + 2 * 144 + 6 * 160 + 2 * 176 + 8) >> 4            # = 146
+    assert orc.cost_subpix(DA, DB, 0, 0, 1, 2) == 16 * (v - 128)
+
+
+@pytest.fixture(scope="module")
+def subpix_problem(orc):
+    rng = np.random.default_rng(71)
+    i1, i2, _ = synth.translated_pair(rng, 40, 24, d=(3, -2), rect=(10, 8), rect_d=(-4, 3))
+    DA, DB = orc.descriptors(orc.gray(i1)), orc.descriptors(orc.gray(i2))
+    f0 = rng.integers(-12, 13, size=(24, 40, 2)).astype(np.int16)
+    c0 = np.array([[orc.cost_subpix(DA, DB, x, y, int(f0[y, x, 0]), int(f0[y, x, 1])) for x in range(40)]
+                   for y in range(24)], np.int32)
+    return DA, DB, f0, c0
+
+
+@pytest.mark.parametrize("dir_code", [0, 1, 2, 3])
+def test_subpix_sweep_is_the_scanline_fixed_point(orc, subpix_problem, dir_code):
+    DA, DB, f0, c0 = subpix_problem
+    f1, c1 = orc.sweep_subpix(DA, DB, f0, c0, dir_code)
+    H, W = DA.shape[:2]
+    for y in range(H):
+        for x in range(W):
+            pred = {0: (x - 1, y), 1: (x + 1, y), 2: (x, y - 1), 3: (x, y + 1)}[dir_code]
+            if not (0 <= pred[0] < W and 0 <= pred[1] < H):
+                assert tuple(f1[y, x]) == tuple(f0[y, x]) and c1[y, x] == c0[y, x]
+                continue
+            g = f1[pred[1], pred[0]]
+            e = orc.cost_subpix(DA, DB, x, y, int(g[0]), int(g[1]))
+            if e < c0[y, x]:
+                assert tuple(f1[y, x]) == tuple(g) and c1[y, x] == e
+            else:
+                assert tuple(f1[y, x]) == tuple(f0[y, x]) and c1[y, x] == c0[y, x]
+
+
+def test_subpix_random_search_invariants(orc, subpix_problem):
+    DA, DB, f0, c0 = subpix_problem
+    H, W = DA.shape[:2]
+    f1, c1 = orc.random_search_subpix(DA, DB, f0, c0, 3, 0, 1, 2, 0xC0FFEE)
+    assert np.all(c1 <= c0) and np.any(c1 < c0)
+    assert np.all(np.abs(f1.astype(np.int32) - f0.astype(np.int32)).max(axis=-1) <= 2)
+    for y in range(H):
+        for x in range(W):
+            assert c1[y, x] == orc.cost_subpix(DA, DB, x, y, int(f1[y, x, 0]), int(f1[y, x, 1]))
+
+
+def test_subpix_refinement_end_to_end(orc):
+    """Refinement never raises a cost above the integer search's, keeps
+    identical frames at zero, and recovers a half-pixel shift better than
+    the integer search can (its best is off by 2 quarter pixels)."""
+    i1, i2, _ = synth.config0()
+    a = orc.match(i1, i2, _prm(orc))
+    b = orc.match(i1, i2, _prm(orc, sub_iters=1, sub_radius=2))
+    assert np.all(b["cost_f"] <= a["cost_f"]) and np.all(b["cost_b"] <= a["cost_b"])
+    assert np.any(b["cost_f"] < a["cost_f"])
+    e = orc.fb_error(b["flow_f"], b["cost_f"], b["flow_b"], b["cost_b"], unit=4)
+    assert np.array_equal(b["mask_f"], (e <= 16).astype(np.uint8))          # eps = 1 px = 4 quarters
+    img = synth._to_u8(synth.noise_texture(np.random.default_rng(72), 64, 96))
+    r = orc.match(img, img, _prm(orc, sub_iters=1, sub_radius=2))
+    assert np.all(r["flow_f"] == 0) and np.all(r["cost_f"] == 0)
+    # half-pixel shift: columns of a 2x-wide blurred texture, even vs odd samples
+    rng = np.random.default_rng(73)
+    S = synth._to_u8(synth.noise_texture(rng, 96, 2 * 128, sigma=3.0))
+    j1, j2 = np.ascontiguousarray(S[:, 0::2]), np.ascontiguousarray(S[:, 1::2])
+    ri = orc.match(j1, j2, _prm(orc))
+    rs = orc.match(j1, j2, _prm(orc, sub_iters=2, sub_radius=2))
+    inner = (slice(12, 84), slice(12, 116))
+    err_int = np.abs(4 * ri["flow_f"][inner][..., 0].astype(np.int32) + 2)
+    err_sub = np.abs(rs["flow_f"][inner][..., 0].astype(np.int32) + 2)
+    assert err_int.mean() == 2.0 and err_sub.mean() < 0.5
