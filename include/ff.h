@@ -71,6 +71,15 @@ typedef enum {
 #define FF_SECOND_CHECK 4u  /* two consistency checks (Sec. 3.1): the search runs a
                                second time keyed by seed2, and a match must also be
                                consistent with that search's inverse field        */
+#define FF_SUBPIXEL 8u      /* sub-pixel refinement (Sec. 3.1): after the integer
+                               search, sub_iters more iterations at level 0 on flows
+                               in quarter pixels, the cost of a quarter-pixel target
+                               taken on B's descriptors interpolated bilinearly
+                               (integer weights (4-ax)(4-ay), ax(4-ay), (4-ax)ay,
+                               ax ay over the biased bytes, (sum + 8) >> 4); flow
+                               outputs then in quarter pixels, fberr in 1/16 px^2,
+                               the consistency target rounded half up to whole
+                               pixels; descriptor cost only; W, H <= 2048         */
 
 /* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 and s = 7 for
  * KITTI, epsilon = 7 and s = 4 for MPI Sintel). */
@@ -87,6 +96,9 @@ typedef struct {
                                (7); read only with FF_SPARSIFY                 */
     uint64_t seed2;         /* random-search key of the second search; read
                                only with FF_SECOND_CHECK                       */
+    int32_t  sub_iters;     /* FF_SUBPIXEL: refinement iterations, 1..16 (1)    */
+    int32_t  sub_radius;    /* FF_SUBPIXEL: random-search radius in quarter
+                               pixels, 0..64 (2: trials at 1/2 and 1/4 px)     */
 } ff_params;
 
 /* One image pair and its outputs.  Both frames are [H][W][C] uint8,
@@ -190,7 +202,8 @@ ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n);
  * events, writes one entry per kernel (launch count and summed device time
  * between its events) into out[0..max), returns the number of entries, and
  * clears the record.  Names: gray, down2, desc, seed_records, seed_nn, init,
- * row_phase, col_phase, transpose, fb.  Returns -1 on error.                */
+ * row_phase, col_phase, transpose, fb, sparse, census, save_state,
+ * to_quarter, sub_row_phase, sub_col_phase.  Returns -1 on error.          */
 typedef struct {
     char    name[32];
     int32_t launches;
@@ -209,7 +222,8 @@ typedef enum {
     FF_STAGE_STATE = 4,     /* direction `dir`, level, iter, step: [H_l][W_l] of
                                {int16 dx, int16 dy, int32 cost}; step 0 = after init
                                (iter ignored), 1 LR, 2 RL, 3 RS0, 4 TB, 5 RS1, 6 BT,
-                               7 RS2                                                 */
+                               7 RS2; with FF_SUBPIXEL, level = levels names the
+                               refinement (step 0 = flows in quarter pixels)        */
     FF_STAGE_CENSUS = 5     /* image `image` level `level`: [H_l][W_l] uint64 Census
                                strings (handles created with FF_COST_CENSUS)         */
 } ff_stage_kind;

@@ -58,6 +58,7 @@ struct SearchConst {
     int trials;                      // floor(log2 radius) + 1, 0 when radius == 0
     int eps2;
     uint32_t key0, key1;             // Philox key words
+    int rng_level;                   // >= 0: level word of the Philox counter (sub-pixel refinement)
 };
 
 }  // namespace ff

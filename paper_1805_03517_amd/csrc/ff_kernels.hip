@@ -98,6 +98,50 @@ template <> struct Feat<1> {
     __device__ static int32_t dist(T a, T b) { return (int32_t)(__popc(a.x ^ b.x) + __popc(a.y ^ b.y)); }
 };
 
+// Sub-pixel refinement (Sec. 3.1): flows in quarter pixels, own feature =
+// the pixel's descriptor; the cost is computed by subpix_cost below.
+template <> struct Feat<2> {
+    using T = uint4;
+    __device__ static T load(gcu8* __restrict__ base, size_t idx) { return ld16(base + idx * 16); }
+    __device__ static T zero() { return make_uint4(0, 0, 0, 0); }
+};
+
+// Bilinear interpolation of one word of four biased descriptor bytes with
+// integer weights summing to 16, rounded half up: even and odd bytes as
+// 16-bit lanes (each lane's sum <= 16 * 255 + 8, so 32-bit arithmetic on the
+// packed pairs never carries between lanes).
+__device__ __forceinline__ uint32_t bilerp_word(uint32_t b00, uint32_t b10, uint32_t b01, uint32_t b11, uint32_t w00,
+                                                uint32_t w10, uint32_t w01, uint32_t w11)
+{
+    const uint32_t m = 0x00FF00FFu;
+    const uint32_t ev = (b00 & m) * w00 + (b10 & m) * w10 + (b01 & m) * w01 + (b11 & m) * w11 + 0x00080008u;
+    const uint32_t od = ((b00 >> 8) & m) * w00 + ((b10 >> 8) & m) * w10 + ((b01 >> 8) & m) * w01 +
+                        ((b11 >> 8) & m) * w11 + 0x00080008u;
+    return ((ev >> 4) & m) | (((od >> 4) & m) << 8);
+}
+
+// Cost of pixel (x, y) with own descriptor a under quarter-pixel flow f: the
+// target (4x + u, 4y + v) must lie in [0, 4(W-1)] x [0, 4(H-1)]; B's 2x2
+// neighbourhood is interpolated with weights (4-ax)(4-ay), ax(4-ay),
+// (4-ax)ay, ax ay; a neighbour of zero weight is not read.  INF outside.
+template <bool COL>
+__device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f, uint4 a)
+{
+    const int tx = 4 * x + flow_x(f), ty = 4 * y + flow_y(f);
+    if (tx < 0 || ty < 0) return kInf;
+    const int ix = tx >> 2, iy = ty >> 2, ax = tx & 3, ay = ty & 3;
+    if (ix > W - 1 || iy > H - 1 || (ix == W - 1 && ax) || (iy == H - 1 && ay)) return kInf;
+    const int ix1 = ax ? ix + 1 : ix, iy1 = ay ? iy + 1 : iy;
+    const uint4 b00 = ld16(DB + pix<COL>(ix, iy, W, H) * 16), b10 = ld16(DB + pix<COL>(ix1, iy, W, H) * 16);
+    const uint4 b01 = ld16(DB + pix<COL>(ix, iy1, W, H) * 16), b11 = ld16(DB + pix<COL>(ix1, iy1, W, H) * 16);
+    const uint32_t w00 = (4 - ax) * (4 - ay), w10 = ax * (4 - ay), w01 = (4 - ax) * ay, w11 = ax * ay;
+    const uint4 i = make_uint4(bilerp_word(b00.x, b10.x, b01.x, b11.x, w00, w10, w01, w11),
+                               bilerp_word(b00.y, b10.y, b01.y, b11.y, w00, w10, w01, w11),
+                               bilerp_word(b00.z, b10.z, b01.z, b11.z, w00, w10, w01, w11),
+                               bilerp_word(b00.w, b10.w, b01.w, b11.w, w00, w10, w01, w11));
+    return sad16(a, i);
+}
+
 // Matching cost of pixel (x, y) of A, feature a, under flow f against the
 // feature plane DB of B (layout by COL); INF when the target leaves the
 // image, and then no load is issued.
@@ -105,9 +149,13 @@ template <bool COL, int CK>
 __device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f,
                                              typename Feat<CK>::T a)
 {
-    const int qx = x + flow_x(f), qy = y + flow_y(f);
-    if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-    return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)));
+    if constexpr (CK == 2) {
+        return subpix_cost<COL>(DB, W, H, x, y, f, a);
+    } else {
+        const int qx = x + flow_x(f), qy = y + flow_y(f);
+        if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
+        return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)));
+    }
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4-word S-P network,
@@ -914,8 +962,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                                          int iter, int upto, SearchConst sc, int xw, int finit)
 {
     static_assert(!STG || CK == 0, "the staged random search holds descriptors");
+    static_assert(CK != 2 || RC == 0, "the sub-pixel refinement runs the generic pass");
+    const uint32_t rlev = sc.rng_level >= 0 ? (uint32_t)sc.rng_level : (uint32_t)level;   // Philox level word
     using FT = typename Feat<CK>::T;
-    constexpr size_t FB = CK ? 8 : 16;                           // feature bytes per pixel
+    constexpr size_t FB = CK == 1 ? 8 : 16;                      // feature bytes per pixel
     const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int pd = lb / gridDim.x, bx = lb % gridDim.x;
     const PairDev& P = pairs[pd >> 1];
@@ -938,10 +988,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
-    gcu8* __restrict__ DA = (gcu8*)(CK ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
+    gcu8* __restrict__ DA = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
                             (size_t)line * len * FB;
-    gcu8* __restrict__ DB = (gcu8*)(CK ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
-                                       : (COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]));
+    gcu8* __restrict__ DB = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
+                                            : (COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]));
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
     constexpr int WIN = 64 * CH;
     const int nwin = (len + WIN - 1) / WIN;
@@ -1111,7 +1161,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                 if (rs) {
                     const FT ac = a[c];
                     if constexpr (STG) {
-                        random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc, [&](uint32_t f) -> int32_t {
+                        random_search<RC>(bf, bc, W, x, y, rlev, ctr2, sc, [&](uint32_t f) -> int32_t {
                             const int qx = x + flow_x(f), qy = y + flow_y(f);
                             if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
                             const int ri = (COL ? qy : qx) - si0, rj = (COL ? qx : qy) - sj0;
@@ -1120,7 +1170,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                             return sad16(ac, ld16(DB + pix<COL>(qx, qy, W, H) * 16));
                         });
                     } else {
-                        random_search<RC>(bf, bc, W, x, y, (uint32_t)level, ctr2, sc,
+                        random_search<RC>(bf, bc, W, x, y, rlev, ctr2, sc,
                                           [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, x, y, f, ac); });
                     }
                 }
@@ -1174,11 +1224,14 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
 // |F(p) + B(q)|^2 <= eps^2.  Writes the caller's flow / cost / mask.
 // Consistency error |F(p) + B(q)|^2, q = p + F(p); INF when either match is
 // invalid (a finite cost means q lies inside the image).  mask = err <= eps^2.
-__device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, int x, int y, i32x2 s)
+// Flows in 1 / 2^shift pixels (shift 2 after the sub-pixel refinement): q is
+// then rounded half up to whole pixels and the error is in 1 / 4^shift px^2.
+__device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, int x, int y, i32x2 s, int shift)
 {
     if (s.y == kInf) return kInf;
     const uint32_t F = (uint32_t)s.x;
-    const int qx = x + flow_x(F), qy = y + flow_y(F);
+    const int half = shift ? 1 << (shift - 1) : 0;
+    const int qx = x + ((flow_x(F) + half) >> shift), qy = y + ((flow_y(F) + half) >> shift);
     const i32x2 t = other[(uint32_t)qy * (uint32_t)W + (uint32_t)qx];
     if (t.y == kInf) return kInf;
     const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
@@ -1190,7 +1243,7 @@ __device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, 
 // the output buffers are 16- and 4-byte aligned; otherwise pixel by pixel.
 // The error plane is written when the table holds one.
 // grid (pixels / 1024, 2 * pairs).
-__global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2)
+__global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
@@ -1214,7 +1267,7 @@ __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, i
         int32_t e[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            e[k] = fb_err(other, W, x, y, s[k]);
+            e[k] = fb_err(other, W, x, y, s[k], shift);
             m |= (e[k] <= eps2 ? 1u : 0u) << (8 * k);
             if (++x == W) { x = 0; ++y; }
         }
@@ -1226,13 +1279,28 @@ __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, i
     }
     for (int i = i0; i < min(i0 + 4, n); ++i) {
         const i32x2 st = own[i];
-        const int32_t e = fb_err(other, W, x, y, st);
+        const int32_t e = fb_err(other, W, x, y, st, shift);
         if (fl) fl[i] = (uint32_t)st.x;
         if (co) co[i] = st.y;
         if (mk) mk[i] = e <= eps2 ? 1 : 0;
         if (er) er[i] = e;
         if (++x == W) { x = 0; ++y; }
     }
+}
+
+// ---------------------------------------------- sub-pixel refinement ----
+// Level-0 flows of both directions to quarter pixels; costs are unchanged
+// (a whole-pixel target has zero fraction).  grid (pixels / 256, 2 * pairs).
+__global__ __launch_bounds__(256) void k_to_quarter(const PairDev* __restrict__ pairs)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[0];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= L.W * L.H) return;
+    gi2* s = (gi2*)L.state[dir] + i;
+    const uint32_t f = (uint32_t)(*s).x;
+    (*s).x = (int)pack_flow(4 * flow_x(f), 4 * flow_y(f));
 }
 
 // --------------------------------------------- second consistency check --
@@ -1253,7 +1321,7 @@ __global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ 
 // search's B2; the error is the larger of the two (INF when either match is
 // invalid) and the mask is error <= eps^2.  Flow and cost come from the first
 // search.  Four pixels per thread as k_fb.  grid (pixels / 1024, 2 * pairs).
-__global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2)
+__global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
@@ -1271,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, 
     int y = i0 / W, x = i0 - y * W;
     for (int i = i0; i < min(i0 + 4, n); ++i) {
         const i32x2 st = own[i];
-        const int32_t e1 = fb_err(inv1, W, x, y, st), e2 = fb_err(inv2, W, x, y, st);
+        const int32_t e1 = fb_err(inv1, W, x, y, st, shift), e2 = fb_err(inv2, W, x, y, st, shift);
         const int32_t e = max(e1, e2);
         if (fl) fl[i] = (uint32_t)st.x;
         if (co) co[i] = st.y;
@@ -1431,17 +1499,21 @@ template <int CK>
 bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
                     int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
-    if (sc.radius == 16)
-        return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
-                   : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit,
-                                                   st);
+    if constexpr (CK != 2) {
+        if (sc.radius == 16)
+            return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0,
+                                                      st)
+                       : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
+                                                       finit, st);
+    }
     return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
                : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
 }
 
 // One row or column phase of every pair and direction at one level.  ch =
 // chunks of 64 px per relaxation window, wpb = lines per block, stg = staged
-// random search, census = Census cost (else descriptor SAD); supported: stg 0
+// random search, ck = cost (0 descriptor SAD, 1 Census, 2 sub-pixel SAD on
+// quarter-pixel flows, generic pass only); supported: stg 0
 // with ch in {1, 2, 4, 8} and wpb in {2, 4, 8} (ch <= 2 runs the
 // software-pipelined pass at radius 16); stg 1, descriptor cost only, with
 // (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false otherwise.
@@ -1452,11 +1524,13 @@ bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int np
 // first pass loads each pixel's init flow and costs it instead of reading a
 // state written by k_init); only the software-pipelined pass supports it --
 // see line_fused_init().
-bool launch_line_phase(bool col, int ch, int wpb, int stg, bool census, const PairDev* d, int npairs, int level,
+bool launch_line_phase(bool col, int ch, int wpb, int stg, int ck, const PairDev* d, int npairs, int level,
                        int iter, int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
-    return census ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st)
-                  : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
+    if (ck == 2)
+        return stg == 0 && launch_line_ck<2>(col, ch, wpb, 0, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
+    return ck ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st)
+              : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
 }
 
 // Whether the row phase with this schedule can take over the level init.
@@ -1470,17 +1544,21 @@ void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, i
     hipLaunchKernelGGL(k_transpose_state, dim3((sw + 31) / 32, (sh + 31) / 32, 2 * npairs), dim3(256), 0, st, d,
                        level, to_t);
 }
-void launch_fb(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
+void launch_fb(const PairDev* d, int npairs, int eps2, int shift, int maxpx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fb, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
+    hipLaunchKernelGGL(k_fb, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2, shift);
+}
+void launch_to_quarter(const PairDev* d, int npairs, int maxpx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_quarter, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
 }
 void launch_save_state(const PairDev* d, int npairs, int maxpx, hipStream_t st)
 {
     hipLaunchKernelGGL(k_save_state, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
 }
-void launch_fb2(const PairDev* d, int npairs, int eps2, int maxpx, hipStream_t st)
+void launch_fb2(const PairDev* d, int npairs, int eps2, int shift, int maxpx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fb2, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2);
+    hipLaunchKernelGGL(k_fb2, dim3((maxpx + 1023) / 1024, 2 * npairs), dim3(256), 0, st, d, eps2, shift);
 }
 void launch_sparse(const PairDev* d, int npairs, int eps2, int s, int maxW, int maxH, hipStream_t st)
 {

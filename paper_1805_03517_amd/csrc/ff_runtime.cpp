@@ -31,15 +31,16 @@ void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, int, hipStream_t);
 void launch_census(const PairDev*, int, int, int, int, hipStream_t);
-bool launch_line_phase(bool, int, int, int, bool, const PairDev*, int, int, int, int, const SearchConst&, int, int,
+bool launch_line_phase(bool, int, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, int,
                        int, hipStream_t);
 bool line_fused_init(int ch, int stg, const SearchConst& sc);
 bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
-void launch_fb(const PairDev*, int, int, int, hipStream_t);
+void launch_fb(const PairDev*, int, int, int, int, hipStream_t);
+void launch_to_quarter(const PairDev*, int, int, hipStream_t);
 void launch_sparse(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_save_state(const PairDev*, int, int, hipStream_t);
-void launch_fb2(const PairDev*, int, int, int, hipStream_t);
+void launch_fb2(const PairDev*, int, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
 }  // namespace ff
@@ -182,7 +183,13 @@ ff_status validate_params(ff_ctx* h, const ff_params& p)
     if (p.iters < 0 || p.iters > 64) return fail(h, FF_ERR_INVALID, "iters must be in 0..64");
     if (p.rs_radius < 0 || p.rs_radius > 1024) return fail(h, FF_ERR_INVALID, "rs_radius must be in 0..1024");
     if (p.fb_eps < 0 || p.fb_eps > 1024) return fail(h, FF_ERR_INVALID, "fb_eps must be in 0..1024");
-    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK)) return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK | FF_SUBPIXEL))
+        return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if (p.flags & FF_SUBPIXEL) {
+        if (p.flags & FF_COST_CENSUS) return fail(h, FF_ERR_INVALID, "FF_SUBPIXEL needs the descriptor cost");
+        if (p.sub_iters < 1 || p.sub_iters > 16) return fail(h, FF_ERR_INVALID, "sub_iters must be in 1..16");
+        if (p.sub_radius < 0 || p.sub_radius > 64) return fail(h, FF_ERR_INVALID, "sub_radius must be in 0..64");
+    }
     if ((p.flags & FF_SPARSIFY) && (p.sparse_min < 1 || p.sparse_min > 9))
         return fail(h, FF_ERR_INVALID, "sparse_min must be in 1..9");
     return FF_OK;
@@ -198,6 +205,8 @@ ff_status validate_pair(ff_ctx* h, const ff_pair& q)
         return fail(h, FF_ERR_INVALID, "width and height must be in 1..8192");
     if ((q.width >> (p.levels - 1)) < 1 || (q.height >> (p.levels - 1)) < 1)
         return fail(h, FF_ERR_INVALID, "image too small for the number of levels");
+    if ((p.flags & FF_SUBPIXEL) && (q.width > 2048 || q.height > 2048))
+        return fail(h, FF_ERR_INVALID, "FF_SUBPIXEL: quarter-pixel flows need width and height <= 2048");
     if (((uintptr_t)q.flow_fwd & 3) || ((uintptr_t)q.flow_bwd & 3) || ((uintptr_t)q.cost_fwd & 3) ||
         ((uintptr_t)q.cost_bwd & 3) || ((uintptr_t)q.fberr_fwd & 3) || ((uintptr_t)q.fberr_bwd & 3))
         return fail(h, FF_ERR_INVALID, "flow, cost and fberr outputs must be 4-byte aligned");
@@ -353,13 +362,16 @@ SearchConst search_const(const ff_params& p)
     sc.eps2 = p.fb_eps * p.fb_eps;
     sc.key0 = (uint32_t)p.seed;
     sc.key1 = (uint32_t)(p.seed >> 32);
+    sc.rng_level = -1;
     return sc;
 }
 
-const char* const kKernelNames[] = {"gray", "down2", "desc", "seed_records", "seed_nn", "init", "row_phase",
-                                    "col_phase", "transpose", "fb", "sparse", "census", "save_state"};
+const char* const kKernelNames[] = {"gray",      "down2",     "desc",       "seed_records", "seed_nn",
+                                    "init",      "row_phase", "col_phase",  "transpose",    "fb",
+                                    "sparse",    "census",    "save_state", "to_quarter",   "sub_row_phase",
+                                    "sub_col_phase"};
 enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_SPARSE,
-       KN_CENSUS, KN_SAVE, KN_COUNT };
+       KN_CENSUS, KN_SAVE, KN_QUARTER, KN_SUB_ROW, KN_SUB_COL, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
@@ -446,6 +458,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     // The search; with FF_SECOND_CHECK it runs again keyed by seed2 after
     // the first search's level-0 state is saved (debug stops name the first).
     const bool second = (p.flags & FF_SECOND_CHECK) != 0;
+    const bool subpix = (p.flags & FF_SUBPIXEL) != 0;
     SearchConst sc2 = sc;
     sc2.key0 = (uint32_t)p.seed2;
     sc2.key1 = (uint32_t)(p.seed2 >> 32);
@@ -467,12 +480,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             for (int t = 0; t < p.iters; ++t) {
                 const bool last = stop_here && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
-                FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census, d, n, l, t,
+                FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census ? 1 : 0, d, n, l, t,
                                                     std::min(upto, 3), scr, D.maxH[l], D.maxW[l], fuse && t == 0, st));
                 if (upto >= 4) {
                     // the column phase reads the row-major state; its result comes
                     // back row-major when the cross write applies, else from stateT
-                    FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census, d, n, l, t, upto, scr,
+                    FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census ? 1 : 0, d, n, l, t, upto, scr,
                                                         D.maxW[l], D.maxH[l], 0, st));
                     if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
                         FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
@@ -484,14 +497,49 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                 }
             }
         }
+        if (subpix) {
+            // sub-pixel refinement at level 0 on quarter-pixel flows; the
+            // debug stops name it as level `levels`
+            FF_TRACED(KN_QUARTER, 0, launch_to_quarter(d, n, D.maxPx[0], st));
+            const bool stop_sub = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == L;
+            if (stop_sub && stop.st.step == 0) {
+                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].state[stop.st.dir], level_px(0) * 8, hipMemcpyDeviceToDevice, st));
+                return FF_OK;
+            }
+            SearchConst scs = scr;
+            scs.radius = p.sub_radius;
+            scs.trials = 0;
+            while ((p.sub_radius >> scs.trials) > 0) ++scs.trials;
+            scs.rng_level = L;
+            for (int t = 0; t < p.sub_iters; ++t) {
+                const bool last = stop_sub && stop.st.iter == t;
+                const int upto = last ? stop.st.step : 7;
+                FF_TRACED(KN_SUB_ROW, 0, launch_line_phase(false, 1, 4, 0, 2, d, n, 0, t, std::min(upto, 3), scs, D.maxH[0],
+                                                           D.maxW[0], 0, st));
+                if (upto >= 4) {
+                    FF_TRACED(KN_SUB_COL, 0, launch_line_phase(true, 1, 8, 0, 2, d, n, 0, t, upto, scs, D.maxW[0], D.maxH[0], 0,
+                                                               st));
+                    if (!line_cross_write(8, D.maxH[0]))
+                        FF_TRACED(KN_TRANS, 0, launch_transpose_state(d, n, 0, 0, D.maxW[0], D.maxH[0], st));
+                }
+                if (last) {
+                    FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].state[stop.st.dir], level_px(0) * 8,
+                                             hipMemcpyDeviceToDevice, st));
+                    return FF_OK;
+                }
+            }
+        }
     }
     if (stop.active) return fail(h, FF_ERR_INVALID, "debug stage names a point the schedule does not reach");
+    // quarter-pixel flows: consistency target rounded to whole pixels, the
+    // error and its threshold in 1/16 px^2
+    const int shift = subpix ? 2 : 0, eps2 = sc.eps2 << (2 * shift);
     if (second)
-        FF_TRACED(KN_FB, 0, launch_fb2(d, n, sc.eps2, D.maxPx[0], st));
+        FF_TRACED(KN_FB, 0, launch_fb2(d, n, eps2, shift, D.maxPx[0], st));
     else
-        FF_TRACED(KN_FB, 0, launch_fb(d, n, sc.eps2, D.maxPx[0], st));
+        FF_TRACED(KN_FB, 0, launch_fb(d, n, eps2, shift, D.maxPx[0], st));
     if (p.flags & FF_SPARSIFY)
-        FF_TRACED(KN_SPARSE, 0, launch_sparse(d, n, sc.eps2, p.sparse_min, D.maxW[0], D.maxH[0], st));
+        FF_TRACED(KN_SPARSE, 0, launch_sparse(d, n, eps2, p.sparse_min, D.maxW[0], D.maxH[0], st));
     return FF_OK;
 }
 
@@ -886,9 +934,10 @@ ff_status ff_debug_stage(ff_handle h, const ff_pair* pair, const ff_stage* which
     if (!h) return FF_ERR_INVALID;
     if (!pair || !which || !dst) return fail(h, FF_ERR_INVALID, "pair, which and dst are required");
     const ff_stage& w = *which;
+    const bool sub_stage = (h->prm.flags & FF_SUBPIXEL) && w.kind == FF_STAGE_STATE && w.level == h->prm.levels;
     if (w.kind < FF_STAGE_GRAY || w.kind > FF_STAGE_CENSUS || w.image < 0 || w.image > 1 || w.dir < 0 ||
-        w.dir > 1 || w.level < 0 || w.level >= h->prm.levels || w.step < 0 || w.step > 7 || w.iter < 0 ||
-        (w.kind == FF_STAGE_STATE && w.step > 0 && w.iter >= h->prm.iters))
+        w.dir > 1 || w.level < 0 || (w.level >= h->prm.levels && !sub_stage) || w.step < 0 || w.step > 7 ||
+        w.iter < 0 || (w.kind == FF_STAGE_STATE && w.step > 0 && w.iter >= (sub_stage ? h->prm.sub_iters : h->prm.iters)))
         return fail(h, FF_ERR_INVALID, "bad debug stage");
     if (w.kind == FF_STAGE_CENSUS && !(h->prm.flags & FF_COST_CENSUS))
         return fail(h, FF_ERR_INVALID, "Census strings exist only with FF_COST_CENSUS");
