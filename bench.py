@@ -36,7 +36,7 @@ SCHEDULE_C1 = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0, 1,
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "2df2e46b917b5d58", "bytes_per_launch": 1870056448}
+TRAFFIC = {"kernel_sha": "b957fa26441600c7", "bytes_per_launch": 1893930444}
 
 
 def kernel_sha():
@@ -276,6 +276,49 @@ def sparse_bench(torch, ff, pairs, steps):
 CEN_COL_BYTES_PER_PX = 12 * 8 + 32     # 12 Census gathers of 8 B, own strings 2 x 8, state in + out
 
 
+def subpix_bench(torch, ff, pairs, steps, sub_iters=1, sub_radius=2):
+    """Sub-pixel refinement (Sec. 3.1) on the benchmark batch: whole-step
+    throughput with it on, and its two line kernels' rate of 16-byte
+    descriptor loads.  A quarter-pixel candidate reads B's 2x2 neighbourhood
+    (4 loads); with radius R the random search makes J = floor(log2 R) + 1
+    trials, so per level-0 pixel, direction and iteration the row phase
+    evaluates 2 + J candidates and the column phase 2 + 2J.  Neighbouring
+    lanes' 2x2 blocks overlap, so most of these loads hit L1/L2: their bytes
+    (64 per candidate) exceed what HBM could deliver, and the load rate, not
+    a byte count, is what these kernels are measured by."""
+    W, H = W0, H0
+    J = sub_radius.bit_length()
+    m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
+                   sub_iters=sub_iters, sub_radius=sub_radius)
+    m.set_tuning(SCHEDULE_C1)
+    outs = [m._outputs(H, W, True, True) for _ in pairs]
+    for _ in range(2):
+        m.match_batch(pairs, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.match_batch(pairs, outs=outs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.profile(True)
+    for _ in range(steps):
+        m.match_batch(pairs, outs=outs)
+    prof = m.profile_read()
+    m.profile(False)
+    frac_px = float(sum(((o["flow_f"] & 3) != 0).any(-1).float().mean().item() for o in outs[:8]) / 8)
+    consistent = float(sum(o["mask_f"].float().mean().item() for o in outs[:8]) / 8)
+    m.close()
+    kern = {}
+    for k, cands in (("sub_row_phase", 2 + J), ("sub_col_phase", 2 + 2 * J)):
+        n, ms = prof[k]
+        avg_s = ms / n / 1000.0
+        loads = 4 * cands * W * H * 2 * len(pairs)
+        kern[k] = {"avg_us": avg_s * 1e6, "candidates_per_px": cands, "loads_per_launch": loads,
+                   "g_loads_per_s": loads / avg_s / 1e9}
+    return {"sub_iters": sub_iters, "sub_radius_quarter_px": sub_radius, "pairs_per_s": len(pairs) * steps / wall,
+            "fractional_flow_fraction_fwd": frac_px, "consistent_fraction_fwd": consistent, "kernels": kern}
+
+
 def census_bench(torch, ff, n_pairs, distinct, steps):
     """Census cost (Sec. 3.1; the paper's Sintel cost, eps = 7 from Table 3)
     on a batch of Sintel-shaped 1024x436 RGB pairs, against the descriptor
@@ -382,7 +425,7 @@ def main():
     ap.add_argument("--no-census", action="store_true", help="skip the Census-cost leg")
     ap.add_argument("--core", action="store_true",
                     help="only the timed steps and their per-kernel timing (for profiler runs): no seed-search "
-                         "shape, sparsification, Census, serving, config-4 or CPU legs")
+                         "shape, sparsification, sub-pixel, Census, serving, config-4 or CPU legs")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters, then exit")
@@ -494,6 +537,11 @@ def main():
         print("[bench] sparsification leg", file=sys.stderr, flush=True)
         sparse = sparse_bench(torch, ff, pairs, max(2, args.steps // 4))
 
+    subpix = None
+    if not args.core:
+        print("[bench] sub-pixel refinement leg", file=sys.stderr, flush=True)
+        subpix = subpix_bench(torch, ff, pairs, max(2, args.steps // 4))
+
     census = None
     if not args.no_census:
         print("[bench] Census-cost leg (Sintel-shaped batch)", file=sys.stderr, flush=True)
@@ -545,6 +593,7 @@ def main():
         "plain": plain,
         "seed_nn": seednn,
         "sparsify": sparse,
+        "subpixel": subpix,
         "census": census,
         "serving": serving,
         "batch_c4": batch_c4,

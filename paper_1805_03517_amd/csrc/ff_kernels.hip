@@ -123,7 +123,9 @@ __device__ __forceinline__ uint32_t bilerp_word(uint32_t b00, uint32_t b10, uint
 // Cost of pixel (x, y) with own descriptor a under quarter-pixel flow f: the
 // target (4x + u, 4y + v) must lie in [0, 4(W-1)] x [0, 4(H-1)]; B's 2x2
 // neighbourhood is interpolated with weights (4-ax)(4-ay), ax(4-ay),
-// (4-ax)ay, ax ay; a neighbour of zero weight is not read.  INF outside.
+// (4-ax)ay, ax ay.  A neighbour of zero weight is replaced by the pixel
+// itself, so no read leaves the image (four loads whatever the fraction:
+// skipping them per lane measured slower).  INF outside.
 template <bool COL>
 __device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f, uint4 a)
 {
@@ -1034,6 +1036,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const int sstr = (COL && fwd) ? W : 1;
         const bool lin = xwk && (COL || !fwd);
         const bool lout = xwk && (COL || (fwd && upto >= 2));
+        const bool quarter = CK == 2 && !COL && fwd && finit;
 
         if constexpr (!STG && RC > 0 && CH <= 2) {
             if (active)
@@ -1056,6 +1059,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                 const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
                 a[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
                 f0[c] = (uint32_t)st.x;
+                // first row pass of the refinement: whole-pixel flows to
+                // quarter pixels on load (costs unchanged, zero fraction)
+                if constexpr (CK == 2)
+                    if (quarter) f0[c] = pack_flow(4 * flow_x(f0[c]), 4 * flow_y(f0[c]));
                 c0[c] = st.y;
                 hp[c] = valid && (fwd ? p > 0 : p + 1 < len);
                 lp[c] = f0[c];
@@ -1320,7 +1327,8 @@ __global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ 
 // checked against the first search's inverse field B and the second
 // search's B2; the error is the larger of the two (INF when either match is
 // invalid) and the mask is error <= eps^2.  Flow and cost come from the first
-// search.  Four pixels per thread as k_fb.  grid (pixels / 1024, 2 * pairs).
+// search.  Four pixels per thread with 16-byte state loads and vector stores
+// when aligned, as k_fb.  grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
@@ -1337,10 +1345,28 @@ __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, 
     uint8_t* mk = P.mask[dir];
     int32_t* er = P.fberr[dir];
     int y = i0 / W, x = i0 - y * W;
+    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0 &&
+        ((uintptr_t)er & 15u) == 0) {
+        const u32x4 s01 = *(gcu4*)(own + i0), s23 = *(gcu4*)(own + i0 + 2);
+        const i32x2 s[4] = {i32x2{(int)s01.x, (int)s01.y}, i32x2{(int)s01.z, (int)s01.w},
+                            i32x2{(int)s23.x, (int)s23.y}, i32x2{(int)s23.z, (int)s23.w}};
+        uint32_t m = 0;
+        int32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            e[k] = max(fb_err(inv1, W, x, y, s[k], shift), fb_err(inv2, W, x, y, s[k], shift));
+            m |= (e[k] <= eps2 ? 1u : 0u) << (8 * k);
+            if (++x == W) { x = 0; ++y; }
+        }
+        if (er) *(FF_GLOBAL u32x4*)(er + i0) = u32x4{(uint32_t)e[0], (uint32_t)e[1], (uint32_t)e[2], (uint32_t)e[3]};
+        if (fl) *(FF_GLOBAL u32x4*)(fl + i0) = u32x4{(uint32_t)s[0].x, (uint32_t)s[1].x, (uint32_t)s[2].x, (uint32_t)s[3].x};
+        if (co) *(FF_GLOBAL u32x4*)(co + i0) = u32x4{(uint32_t)s[0].y, (uint32_t)s[1].y, (uint32_t)s[2].y, (uint32_t)s[3].y};
+        if (mk) *(FF_GLOBAL uint32_t*)(mk + i0) = m;
+        return;
+    }
     for (int i = i0; i < min(i0 + 4, n); ++i) {
         const i32x2 st = own[i];
-        const int32_t e1 = fb_err(inv1, W, x, y, st, shift), e2 = fb_err(inv2, W, x, y, st, shift);
-        const int32_t e = max(e1, e2);
+        const int32_t e = max(fb_err(inv1, W, x, y, st, shift), fb_err(inv2, W, x, y, st, shift));
         if (fl) fl[i] = (uint32_t)st.x;
         if (co) co[i] = st.y;
         if (mk) mk[i] = e <= eps2 ? 1 : 0;
@@ -1507,7 +1533,8 @@ bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int np
                                                        finit, st);
     }
     return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
-               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
+               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
+                                              CK == 2 ? finit : 0, st);
 }
 
 // One row or column phase of every pair and direction at one level.  ch =
@@ -1528,7 +1555,7 @@ bool launch_line_phase(bool col, int ch, int wpb, int stg, int ck, const PairDev
                        int iter, int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
     if (ck == 2)
-        return stg == 0 && launch_line_ck<2>(col, ch, wpb, 0, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
+        return stg == 0 && launch_line_ck<2>(col, ch, wpb, 0, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
     return ck ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st)
               : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
 }

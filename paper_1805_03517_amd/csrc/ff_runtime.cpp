@@ -498,14 +498,18 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             }
         }
         if (subpix) {
-            // sub-pixel refinement at level 0 on quarter-pixel flows; the
-            // debug stops name it as level `levels`
-            FF_TRACED(KN_QUARTER, 0, launch_to_quarter(d, n, D.maxPx[0], st));
+            // sub-pixel refinement at level 0 on quarter-pixel flows (the
+            // debug stops name it as level `levels`); the first row pass
+            // scales the flows to quarter pixels as it loads them, unless a
+            // stop asks for that state itself
             const bool stop_sub = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == L;
             if (stop_sub && stop.st.step == 0) {
+                FF_TRACED(KN_QUARTER, 0, launch_to_quarter(d, n, D.maxPx[0], st));
                 FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].state[stop.st.dir], level_px(0) * 8, hipMemcpyDeviceToDevice, st));
                 return FF_OK;
             }
+            // fixed schedule, (1, 8) rows and (1, 4) columns: the fastest of
+            // the generic-pass shapes measured on the 1242x375 batch
             SearchConst scs = scr;
             scs.radius = p.sub_radius;
             scs.trials = 0;
@@ -514,12 +518,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             for (int t = 0; t < p.sub_iters; ++t) {
                 const bool last = stop_sub && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
-                FF_TRACED(KN_SUB_ROW, 0, launch_line_phase(false, 1, 4, 0, 2, d, n, 0, t, std::min(upto, 3), scs, D.maxH[0],
-                                                           D.maxW[0], 0, st));
+                FF_TRACED(KN_SUB_ROW, 0, launch_line_phase(false, 1, 8, 0, 2, d, n, 0, t, std::min(upto, 3), scs, D.maxH[0],
+                                                           D.maxW[0], t == 0 ? 1 : 0, st));
                 if (upto >= 4) {
-                    FF_TRACED(KN_SUB_COL, 0, launch_line_phase(true, 1, 8, 0, 2, d, n, 0, t, upto, scs, D.maxW[0], D.maxH[0], 0,
+                    FF_TRACED(KN_SUB_COL, 0, launch_line_phase(true, 1, 4, 0, 2, d, n, 0, t, upto, scs, D.maxW[0], D.maxH[0], 0,
                                                                st));
-                    if (!line_cross_write(8, D.maxH[0]))
+                    if (!line_cross_write(4, D.maxH[0]))
                         FF_TRACED(KN_TRANS, 0, launch_transpose_state(d, n, 0, 0, D.maxW[0], D.maxH[0], st));
                 }
                 if (last) {
