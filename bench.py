@@ -464,7 +464,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pairs are independent and a "
-              "multi-GPU run would shard them, which this build does not do", file=sys.stderr)
+              "multi-GPU run would shard them across processes, which is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
