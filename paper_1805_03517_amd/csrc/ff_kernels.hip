@@ -35,7 +35,25 @@ typedef FF_GLOBAL const u32x4 gcu4;
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef FF_GLOBAL const u32x2 gcu2;
 typedef FF_GLOBAL i32x2 gi2;
-typedef __attribute__((address_space(3))) i32x2 li2;
+
+// One line's search state in LDS between a phase's passes: flows as u32 and
+// costs as u16 in two planes (6 bytes a pixel instead of 8, so more lines fit
+// per CU).  Every finite cost fits: SAD of 16 bytes <= 4080, Hamming <= 48;
+// INF is stored as 0xFFFF.
+struct LdsLine {
+    __attribute__((address_space(3))) uint32_t* f;
+    __attribute__((address_space(3))) uint16_t* c;
+    __device__ __forceinline__ i32x2 get(int p) const
+    {
+        const uint32_t cc = c[p];
+        return i32x2{(int)f[p], cc == 0xFFFFu ? kInf : (int)cc};
+    }
+    __device__ __forceinline__ void set(int p, i32x2 v) const
+    {
+        f[p] = (uint32_t)v.x;
+        c[p] = (uint16_t)(v.y == kInf ? 0xFFFFu : (uint32_t)v.y);
+    }
+};
 
 __device__ __forceinline__ uint4 ld16(gcu8* p)
 {
@@ -780,7 +798,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 template <int RC, bool COL, int CH, int CK>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
-                                                    bool lin, bool lout, li2* lline, int W, int H, int len, int line,
+                                                    bool lin, bool lout, LdsLine lline, int W, int H, int len, int line,
                                                     int lane,
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
                                                     const SearchConst& sc, const PairDev& P, int dir, int initc)
@@ -806,7 +824,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     const uint32_t f = init_flow(P, dir, (int)level, initc == 2, sc.stride, W, p, line);
                     st = i32x2{(int)f, feat_cost<false, CK>(DB, W, H, p, line, f, A[c])};
                 } else {
-                    st = lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
+                    st = lin ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
                 }
             }
             F[c] = (uint32_t)st.x;
@@ -834,7 +852,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int32_t e = ((pin[c] >> j) & 1u) ? Feat<CK>::dist(pa[c], pdesc[c][j]) : kInf;
                 if (e < bc) { bc = e; bf = pcand[c][j]; }
             }
-            if (lout) lline[p] = i32x2{(int)bf, bc};
+            if (lout) lline.set(p, i32x2{(int)bf, bc});
             else S[p] = i32x2{(int)bf, bc};
         }
     };
@@ -934,7 +952,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int p = w0 + 64 * c + lane;
                 if (p >= len) continue;
                 const int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
-                if (lout) lline[p] = i32x2{(int)h[c], bc};
+                if (lout) lline.set(p, i32x2{(int)h[c], bc});
                 else S[p] = i32x2{(int)h[c], bc};
             }
         }
@@ -1003,15 +1021,18 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     __shared__ uint4 region[STG ? SD::CAP : 1];
     __shared__ int sample[2][WPB][2];                            // per parity: a flow sample (i, j) per line
     __shared__ int sample_ok[2][WPB];
-    extern __shared__ i32x2 lbuf_[];                             // xw: WPB lines x len
-    li2* const lbuf = (li2*)lbuf_;
-    li2* const lline = lbuf + wave * len;
+    extern __shared__ uint32_t lbuf_[];                          // xw: WPB lines x len, two planes
+    auto line_lds = [&](int k) {
+        __attribute__((address_space(3))) uint32_t* const f = (__attribute__((address_space(3))) uint32_t*)lbuf_;
+        return LdsLine{f + k * len, (__attribute__((address_space(3))) uint16_t*)(f + WPB * len) + k * len};
+    };
+    const LdsLine lline = line_lds(wave);
     if (xwc) {
         const gi2* __restrict__ src = (const gi2*)L.state[dir];
         const int nl = min(WPB, nlines - line0);
         for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
             const int k = e % WPB, p = e / WPB;
-            if (k < nl) lbuf[k * len + p] = src[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)];
+            if (k < nl) line_lds(k).set(p, src[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)]);
         }
         __syncthreads();
     }
@@ -1056,7 +1077,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = active && p < len;
-                const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline[p] : Sin[(uint32_t)p * (uint32_t)sstr];
+                const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
                 a[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
                 f0[c] = (uint32_t)st.x;
                 // first row pass of the refinement: whole-pixel flows to
@@ -1181,7 +1202,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                           [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, x, y, f, ac); });
                     }
                 }
-                if (lout) lline[p] = i32x2{(int)bf, bc};
+                if (lout) lline.set(p, i32x2{(int)bf, bc});
                 else S[p] = i32x2{(int)bf, bc};
             }
         }
@@ -1193,7 +1214,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const int nl = min(WPB, nlines - line0);
         for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
             const int k = e % WPB, p = e / WPB;
-            if (k < nl) dst[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)] = lbuf[k * len + p];
+            if (k < nl) dst[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)] = line_lds(k).get(p);
         }
     }
 }
@@ -1484,11 +1505,13 @@ void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stri
     hipLaunchKernelGGL(k_init, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level, coarsest, stride,
                        census);
 }
-// A line phase keeps its WPB lines' state in LDS between its passes when
-// they fit in 64 KiB (lines up to 1024 px at 8 lines per block, 2048 px at 4).
+// A line phase keeps its WPB lines' state in LDS (6 bytes a pixel) between
+// its passes when they fit in 64 KiB (lines up to 1365 px at 8 lines per
+// block, 2730 px at 4).
+constexpr size_t kLdsBytesPerPx = 6;
 bool line_cross_write(int wpb, int maxlen)
 {
-    return (size_t)wpb * (size_t)maxlen * sizeof(int2) <= 65536;
+    return (size_t)wpb * (size_t)maxlen * kLdsBytesPerPx <= 65536;
 }
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
@@ -1496,7 +1519,7 @@ void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, 
                    int maxlen, int finit, hipStream_t st)
 {
     const int xw = line_cross_write(WPB, maxlen) ? 1 : 0;
-    const size_t dyn = xw ? (size_t)WPB * maxlen * sizeof(int2) : 0;
+    const size_t dyn = xw ? (size_t)WPB * maxlen * kLdsBytesPerPx : 0;
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
                        dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw, finit);
 }
