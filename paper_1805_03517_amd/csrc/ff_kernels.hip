@@ -39,19 +39,23 @@ typedef FF_GLOBAL i32x2 gi2;
 // One line's search state in LDS between a phase's passes: flows as u32 and
 // costs as u16 in two planes (6 bytes a pixel instead of 8, so more lines fit
 // per CU).  Every finite cost fits: SAD of 16 bytes <= 4080, Hamming <= 48;
-// INF is stored as 0xFFFF.
+// INF is stored as 0xFFFF.  Pixels from lo on are held here; a long row keeps
+// its first windows (p < lo) in global memory instead, so that LDS does not
+// cap the number of waves per CU.
 struct LdsLine {
     __attribute__((address_space(3))) uint32_t* f;
     __attribute__((address_space(3))) uint16_t* c;
+    int lo;
+    __device__ __forceinline__ bool has(int p) const { return p >= lo; }
     __device__ __forceinline__ i32x2 get(int p) const
     {
-        const uint32_t cc = c[p];
-        return i32x2{(int)f[p], cc == 0xFFFFu ? kInf : (int)cc};
+        const uint32_t cc = c[p - lo];
+        return i32x2{(int)f[p - lo], cc == 0xFFFFu ? kInf : (int)cc};
     }
     __device__ __forceinline__ void set(int p, i32x2 v) const
     {
-        f[p] = (uint32_t)v.x;
-        c[p] = (uint16_t)(v.y == kInf ? 0xFFFFu : (uint32_t)v.y);
+        f[p - lo] = (uint32_t)v.x;
+        c[p - lo] = (uint16_t)(v.y == kInf ? 0xFFFFu : (uint32_t)v.y);
     }
 };
 
@@ -824,7 +828,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     const uint32_t f = init_flow(P, dir, (int)level, initc == 2, sc.stride, W, p, line);
                     st = i32x2{(int)f, feat_cost<false, CK>(DB, W, H, p, line, f, A[c])};
                 } else {
-                    st = lin ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
+                    st = (lin && lline.has(p)) ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
                 }
             }
             F[c] = (uint32_t)st.x;
@@ -852,7 +856,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int32_t e = ((pin[c] >> j) & 1u) ? Feat<CK>::dist(pa[c], pdesc[c][j]) : kInf;
                 if (e < bc) { bc = e; bf = pcand[c][j]; }
             }
-            if (lout) lline.set(p, i32x2{(int)bf, bc});
+            if (lout && lline.has(p)) lline.set(p, i32x2{(int)bf, bc});
             else S[p] = i32x2{(int)bf, bc};
         }
     };
@@ -952,7 +956,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                 const int p = w0 + 64 * c + lane;
                 if (p >= len) continue;
                 const int32_t bc = le[c] < c0[c] ? le[c] : c0[c];
-                if (lout) lline.set(p, i32x2{(int)h[c], bc});
+                if (lout && lline.has(p)) lline.set(p, i32x2{(int)h[c], bc});
                 else S[p] = i32x2{(int)h[c], bc};
             }
         }
@@ -998,13 +1002,14 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const int line = line0 + wave;
     if (line0 >= nlines) return;                                 // whole block idle: uniform
     const bool active = line < nlines;
-    // Lines' state in LDS between the passes (xw).  Column phase: the block
-    // copies its WPB columns of the row-major state into LDS, both passes
-    // read and write them there, and the block stores them back row-major
-    // (otherwise the first pass reads the row-major state in place and the
-    // passes write stateT).  Row phase: the first pass reads the state from
-    // global memory and leaves its result in LDS, the second pass reads it
-    // there and writes global memory.
+    // Lines' state in LDS between the passes (xw > 0: pixels held per line).
+    // Column phase: the block copies its WPB columns of the row-major state
+    // into LDS, both passes read and write them there, and the block stores
+    // them back row-major (otherwise the first pass reads the row-major state
+    // in place and the passes write stateT).  Row phase: the first pass reads
+    // the state from global memory and leaves its result in LDS, the second
+    // pass reads it there and writes global memory; a row longer than xw
+    // keeps its first windows in global memory between the passes.
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
@@ -1021,10 +1026,11 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     __shared__ uint4 region[STG ? SD::CAP : 1];
     __shared__ int sample[2][WPB][2];                            // per parity: a flow sample (i, j) per line
     __shared__ int sample_ok[2][WPB];
-    extern __shared__ uint32_t lbuf_[];                          // xw: WPB lines x len, two planes
+    extern __shared__ uint32_t lbuf_[];                          // xw: WPB lines x xw pixels, two planes
+    const int lo = (!COL && len > xw) ? (len - xw + WIN - 1) / WIN * WIN : 0;
     auto line_lds = [&](int k) {
         __attribute__((address_space(3))) uint32_t* const f = (__attribute__((address_space(3))) uint32_t*)lbuf_;
-        return LdsLine{f + k * len, (__attribute__((address_space(3))) uint16_t*)(f + WPB * len) + k * len};
+        return LdsLine{f + k * xw, (__attribute__((address_space(3))) uint16_t*)(f + WPB * xw) + k * xw, lo};
     };
     const LdsLine lline = line_lds(wave);
     if (xwc) {
@@ -1077,7 +1083,9 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
             for (int c = 0; c < CH; ++c) {
                 const int p = w0 + 64 * c + lane;
                 const bool valid = active && p < len;
-                const i32x2 st = !valid ? i32x2{0, kInf} : lin ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
+                const i32x2 st = !valid                    ? i32x2{0, kInf}
+                                 : (lin && lline.has(p)) ? lline.get(p)
+                                                         : Sin[(uint32_t)p * (uint32_t)sstr];
                 a[c] = valid ? Feat<CK>::load(DA, p) : Feat<CK>::zero();
                 f0[c] = (uint32_t)st.x;
                 // first row pass of the refinement: whole-pixel flows to
@@ -1202,7 +1210,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                           [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, x, y, f, ac); });
                     }
                 }
-                if (lout) lline.set(p, i32x2{(int)bf, bc});
+                if (lout && lline.has(p)) lline.set(p, i32x2{(int)bf, bc});
                 else S[p] = i32x2{(int)bf, bc};
             }
         }
@@ -1514,12 +1522,24 @@ bool line_cross_write(int wpb, int maxlen)
     return (size_t)wpb * (size_t)maxlen * kLdsBytesPerPx <= 65536;
 }
 
+// Pixels of a row held in LDS: as many whole windows as let the 24 waves
+// per CU that the line kernels' registers allow share the CU's 160 KiB of LDS;
+// the rest of a longer row goes through global memory between the passes.
+template <int CH, int WPB>
+int row_lds_pixels(int maxlen)
+{
+    constexpr int kWaves = 24, blocks = (kWaves + WPB - 1) / WPB;
+    constexpr int cap = (int)(160 * 1024 / blocks / WPB / kLdsBytesPerPx) / (64 * CH) * (64 * CH);
+    static_assert(cap >= 64 * CH, "at least one window per row in LDS");
+    return maxlen < cap ? maxlen : cap;
+}
+
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
                    int maxlen, int finit, hipStream_t st)
 {
-    const int xw = line_cross_write(WPB, maxlen) ? 1 : 0;
-    const size_t dyn = xw ? (size_t)WPB * maxlen * kLdsBytesPerPx : 0;
+    const int xw = !line_cross_write(WPB, maxlen) ? 0 : COL ? maxlen : row_lds_pixels<CH, WPB>(maxlen);
+    const size_t dyn = (size_t)WPB * xw * kLdsBytesPerPx;
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
                        dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw, finit);
 }
