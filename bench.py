@@ -209,11 +209,14 @@ def seednn_bench(torch, ff, pair, batch_prof):
     and add of the 16-deep dot products); the kernel issues 4x that (K = 64
     MFMA holding [a, a, g] . [b, b, beta]).  Reported for the grouped launch of
     the benchmark batch and for a large shape: one full-resolution 1242x375
-    level (levels = 1), Q = 51750 seeds x N = 465750 pixels, both directions."""
+    level (levels = 1), Q = 51750 seeds x N = 465750 pixels, both directions.
+    The tie-resolving pass that follows it (one chunk of 256 entries per seed)
+    is reported beside it as resolve_us."""
     q, n = seed_counts(W0, H0, LEVELS)
     launches, ms, nbatch = batch_prof
     per_launch = nbatch * 2 * q * n * 16 * 2
-    grouped = {"useful_tops": per_launch / (ms / launches * 1e-3) / 1e12, "avg_us": 1000.0 * ms / launches}
+    grouped = {"useful_tops": per_launch / (ms / launches * 1e-3) / 1e12, "avg_us": 1000.0 * ms / launches,
+               "resolve_us": batch_prof[3]}
     grouped["issued_tops"] = 4 * grouped["useful_tops"]
     m = ff.Matcher(levels=1, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
     a, b = pair
@@ -227,8 +230,10 @@ def seednn_bench(torch, ff, pair, batch_prof):
     m.close()
     ql, nl = seed_counts(W0, H0, 1)
     lw, lms = prof["seed_nn"]
+    rw, rms = prof["seed_resolve"]
     useful = 2 * ql * nl * 16 * 2 / (lms / lw * 1e-3) / 1e12
-    large = {"Q": ql, "N": nl, "avg_us": 1000.0 * lms / lw, "useful_tops": useful, "issued_tops": 4 * useful}
+    large = {"Q": ql, "N": nl, "avg_us": 1000.0 * lms / lw, "useful_tops": useful, "issued_tops": 4 * useful,
+             "resolve_us": 1000.0 * rms / rw}
     for d in (grouped, large):
         d["useful_frac"] = d["useful_tops"] / I8_PEAK_TOPS
         d["issued_frac"] = d["issued_tops"] / I8_PEAK_TOPS
@@ -460,7 +465,7 @@ def main():
         from paper_1805_03517_amd import ff, synth
         a, b = synth.config1(seed=1)[:2]
         pair = (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
-        print(json.dumps(seednn_bench(torch, ff, pair, (1, 1.0, 0))["large_shape"]), flush=True)
+        print(json.dumps(seednn_bench(torch, ff, pair, (1, 1.0, 0, 0.0))["large_shape"]), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pairs are independent and a "
@@ -533,7 +538,8 @@ def main():
     if not args.core:
         print("[bench] seed search MFMA utilisation", file=sys.stderr, flush=True)
         sl, sms = prof.get("seed_nn", (1, 0.0))
-        seednn = seednn_bench(torch, ff, pairs[0], (sl, sms, args.batch))
+        rl, rms = prof.get("seed_resolve", (1, 0.0))
+        seednn = seednn_bench(torch, ff, pairs[0], (sl, sms, args.batch, 1000.0 * rms / rl))
 
     plain = None
     if args.plain:

@@ -203,7 +203,8 @@ ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n);
  * between its events) into out[0..max), returns the number of entries, and
  * clears the record.  Names: gray, down2, desc, seed_records, seed_nn, init,
  * row_phase, col_phase, transpose, fb, sparse, census, save_state,
- * to_quarter, sub_row_phase, sub_col_phase.  Returns -1 on error.          */
+ * to_quarter, sub_row_phase, sub_col_phase, seed_resolve.  Returns -1 on
+ * error.                                                                    */
 typedef struct {
     char    name[32];
     int32_t launches;

@@ -585,12 +585,14 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
 // one split of the database: chunks of kSeedChunk tiles are copied once per
 // block into LDS (direct global -> LDS loads) and read by all four waves, so
 // the database crosses L2 once per block instead of once per wave.  Per lane
-// and seed row a wave keeps max((score << 11) | (2047 - t)), so equal scores
-// prefer the lower tile, then reduces over the 16 columns preferring the
-// lower column, and merges splits with a 64-bit atomicMax on
-// (score + 2^20) << 32 | ~index -- the lowest index wins every tie.
+// and seed row a wave keeps each chunk's largest score (one v_max3 per two
+// scores) and folds it into max((score << 11) | (2047 - chunk)), so equal
+// scores prefer the earlier chunk; splits merge (score, chunk) per seed and
+// k_seed_resolve picks the lowest index inside the winning chunk -- the
+// lowest index wins every tie.
 // grid (ceil(seed tiles / 4), splits, 2 * pairs), 256 threads.
 constexpr int kSeedChunk = 16;                                   // tiles (16 KiB) per LDS chunk
+constexpr int kNoScore = -(1 << 20);                             // below every score; << 11 gives INT32_MIN
 
 template <int MQ>
 __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pairs, int level,
@@ -648,66 +650,117 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        // full tiles two at a time: key = (score << 11) | (2047 - local tile),
-        // one v_lshl_or per score and one v_max3 per two scores
+        // the chunk's largest score per lane and seed row: one v_max3 per two
+        // scores, full tiles two at a time
         const int tfull = min(tb + nt, N >> 4);
+        int cm[MQ][4];
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cm[mq][i] = kNoScore;
         int t = tb;
         for (; t + 1 < tfull; t += 2) {
             const v4i B0 = tiles[(uint32_t)(t - tb) * 64u + lane_off];
             const v4i B1 = tiles[(uint32_t)(t - tb) * 64u + 64u + lane_off];
-            const uint32_t tl0 = (uint32_t)(2047 - (t - t0)), tl1 = tl0 - 1u;
 #pragma unroll
             for (int mq = 0; mq < MQ; ++mq) {
                 const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
                 const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k0 = (int)(((uint32_t)acc0[i] << 11) | tl0);
-                    const int k1 = (int)(((uint32_t)acc1[i] << 11) | tl1);
-                    best[mq][i] = max(best[mq][i], max(k0, k1));
-                }
+                for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], max(acc0[i], acc1[i]));
             }
         }
         // remaining tile of the chunk, possibly the ragged last one of the plane
         for (; t < tb + nt; ++t) {
             const bool nvalid = t * 16 + m < N;
             const v4i B = tiles[(uint32_t)(t - tb) * 64u + lane_off];
-            const uint32_t tl = (uint32_t)(2047 - (t - t0));
 #pragma unroll
             for (int mq = 0; mq < MQ; ++mq) {
                 const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int key = nvalid ? (int)(((uint32_t)acc[i] << 11) | tl) : INT32_MIN;
-                    best[mq][i] = max(best[mq][i], key);
-                }
+                for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], nvalid ? acc[i] : kNoScore);
             }
         }
+        // key = (score << 11) | (2047 - chunk): equal scores prefer the earlier chunk
+        const uint32_t tag = (uint32_t)(2047 - (tb - t0) / kSeedChunk);
+#pragma unroll
+        for (int mq = 0; mq < MQ; ++mq)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) best[mq][i] = max(best[mq][i], (int)(((uint32_t)cm[mq][i] << 11) | tag));
         __syncthreads();                                         // chunk consumed before it is overwritten
     }
     if (qbase >= Q) return;
+    // Per seed: the best key over its 16 columns; splits merge (score, first
+    // tile of the chunk) with a 64-bit atomicMax on (score + 2^20) << 32 |
+    // ~tile, so the merged key names the earliest chunk reaching the best
+    // score.  k_seed_resolve then finds the lowest index inside that chunk.
 #pragma unroll
     for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             int k = best[mq][i];
-            int j = m;
 #pragma unroll
-            for (int off = 1; off < 16; off <<= 1) {
-                const int ok = __shfl_xor(k, off, 64);
-                const int oj = __shfl_xor(j, off, 64);
-                if (ok > k || (ok == k && oj < j)) { k = ok; j = oj; }
-            }
+            for (int off = 1; off < 16; off <<= 1) k = max(k, __shfl_xor(k, off, 64));
             const int q = qbase + 16 * mq + 4 * g + i;
-            if (m == 0 && q < Q && k != INT32_MIN) {
-                const int tloc = 2047 - (k & 2047);
-                const uint32_t n = (uint32_t)((t0 + tloc) * 16 + j);
-                const int score = k >> 11;
+            if (m == 0 && q < Q && (k >> 11) != kNoScore) {
+                const uint32_t tb = (uint32_t)(t0 + (2047 - (k & 2047)) * kSeedChunk);
                 const unsigned long long key =
-                    ((unsigned long long)(uint32_t)(score + (1 << 20)) << 32) | (unsigned long long)(0xFFFFFFFFu - n);
+                    ((unsigned long long)(uint32_t)((k >> 11) + (1 << 20)) << 32) | (unsigned long long)(0xFFFFFFFFu - tb);
                 atomicMax(&P.keys[dir][q], key);
             }
         }
+}
+
+// The lowest database index reaching each seed's best score: the merged key
+// holds the score and the first tile of the earliest chunk reaching it, so
+// the answer is the first of that chunk's 256 entries (16 tiles) with the
+// score, evaluated from the int8 descriptors as 2 a.b - |b|^2 with v_dot4 (the
+// integer the MFMA forms).  Entries past the chunk's split come later than
+// every entry of the chunk, so scanning all 16 tiles finds the same first
+// one.  The key's low word becomes ~index.  One wave per seed, four entries
+// per lane; grid (ceil(seeds / 4), 2 * pairs), 256 threads.
+__global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict__ pairs, int level, int stride)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int dir = blockIdx.y & 1;
+    const LevelDev& L = P.lv[level];
+    const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= Q) return;                                          // wave-uniform
+    const unsigned long long key = P.keys[dir][q];
+    const int S = (int)(uint32_t)(key >> 32) - (1 << 20);
+    const uint32_t tb = 0xFFFFFFFFu - (uint32_t)key;
+    const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
+    const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
+    const int a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
+              a3 = (int)(ad.w ^ 0x80808080u);
+    gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
+    uint4 bd[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t n = tb * 16u + (uint32_t)(64 * c + lane);
+        bd[c] = n < (uint32_t)N ? load_desc(DBd, n) : make_uint4(0, 0, 0, 0);
+    }
+    uint32_t nmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int c = 3; c >= 0; --c) {
+        const uint32_t n = tb * 16u + (uint32_t)(64 * c + lane);
+        const int b0 = (int)(bd[c].x ^ 0x80808080u), b1 = (int)(bd[c].y ^ 0x80808080u),
+                  b2 = (int)(bd[c].z ^ 0x80808080u), b3 = (int)(bd[c].w ^ 0x80808080u);
+        int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
+        ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
+        ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
+        ab = __builtin_amdgcn_sdot4(a3, b3, ab, false);
+        int bb = __builtin_amdgcn_sdot4(b0, b0, 0, false);
+        bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
+        bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
+        bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
+        if (n < (uint32_t)N && 2 * ab - bb == S) nmin = n;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, off, 64));
+    if (lane == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
 }
 
 // ----------------------------------------------------------- level init --
@@ -1486,6 +1539,10 @@ void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, 
 {
     hipLaunchKernelGGL(k_census, dim3((maxW + kCenTX - 1) / kCenTX, (maxH + kCenTY - 1) / kCenTY, 2 * npairs),
                        dim3(256), 0, st, d, level);
+}
+void launch_seed_resolve(const PairDev* d, int npairs, int level, int stride, int maxQ, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 3) / 4, 2 * npairs), dim3(256), 0, st, d, level, stride);
 }
 void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
 {

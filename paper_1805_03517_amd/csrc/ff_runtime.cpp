@@ -29,6 +29,7 @@ void launch_down2(const PairDev*, int, int, int, hipStream_t);
 void launch_desc(const PairDev*, int, int, int, int, hipStream_t);
 void launch_seed_records(const PairDev*, int, int, int, hipStream_t);
 void launch_seed_nn(const PairDev*, int, int, int, int, int, hipStream_t);
+void launch_seed_resolve(const PairDev*, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, int, hipStream_t);
 void launch_census(const PairDev*, int, int, int, int, hipStream_t);
 bool launch_line_phase(bool, int, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, int,
@@ -369,9 +370,9 @@ SearchConst search_const(const ff_params& p)
 const char* const kKernelNames[] = {"gray",      "down2",     "desc",       "seed_records", "seed_nn",
                                     "init",      "row_phase", "col_phase",  "transpose",    "fb",
                                     "sparse",    "census",    "save_state", "to_quarter",   "sub_row_phase",
-                                    "sub_col_phase"};
+                                    "sub_col_phase", "seed_resolve"};
 enum { KN_GRAY, KN_DOWN2, KN_DESC, KN_SEED_REC, KN_SEED_NN, KN_INIT, KN_ROW, KN_COL, KN_TRANS, KN_FB, KN_SPARSE,
-       KN_CENSUS, KN_SAVE, KN_QUARTER, KN_SUB_ROW, KN_SUB_COL, KN_COUNT };
+       KN_CENSUS, KN_SAVE, KN_QUARTER, KN_SUB_ROW, KN_SUB_COL, KN_SEED_RES, KN_COUNT };
 
 // Record the opening event of a traced launch; returns the pair index or -1.
 long prof_begin(ff_ctx* h, int kernel, int level, hipStream_t st)
@@ -451,6 +452,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     }
     FF_TRACED(KN_SEED_REC, c, launch_seed_records(d, n, c, D.maxPx[c], st));
     FF_TRACED(KN_SEED_NN, c, launch_seed_nn(d, n, c, p.seed_stride, D.maxQ, D.maxPx[c], st));
+    FF_TRACED(KN_SEED_RES, c, launch_seed_resolve(d, n, c, p.seed_stride, D.maxQ, st));
     if (stop.active && stop.st.kind == FF_STAGE_SEEDS) {
         launch_keys_to_index(tab0->keys[stop.st.dir], (int32_t*)stop.dst, plan0->nsx * plan0->nsy, st);
         return FF_OK;

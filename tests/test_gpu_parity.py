@@ -211,6 +211,35 @@ def test_periodic_texture_seed_ties(torch, ffm, orc):
     _run_pair(torch, ffm, orc, i1, i2, p, "periodic texture")
 
 
+@pytest.mark.parametrize("kind", ["flat", "stripes", "two_level"])
+def test_seed_ties_within_and_across_chunks(torch, ffm, orc, kind):
+    """Whole-plane ties at one level (levels = 1, 300x200: N = 60000 pixels,
+    30 database splits of 8 LDS chunks): a flat image makes every score
+    equal, vertical stripes repeat every column's descriptor down the plane,
+    a two-level noise image leaves few distinct descriptors.  Every seed
+    must take the lowest tied linear index, exactly as the oracle."""
+    rng = np.random.default_rng(31)
+    if kind == "flat":
+        i1 = np.full((200, 300), 77, np.uint8)
+        i2 = np.full((200, 300), 77, np.uint8)
+    elif kind == "stripes":
+        row = rng.integers(0, 256, size=300, dtype=np.uint8)
+        i1 = np.tile(row, (200, 1))
+        i2 = np.roll(i1, 3, axis=1).copy()
+    else:
+        i1 = (rng.integers(0, 2, size=(200, 300)) * 200 + 20).astype(np.uint8)
+        i2 = np.roll(i1, (2, -1), axis=(0, 1)).copy()
+    p = _prm(orc, levels=1)
+    m = _matcher(ffm, p)
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    D = [orc.descriptors(orc.gray(x)) for x in (i1, i2)]
+    for d in (0, 1):
+        say("seed ties", kind, "dir", d)
+        s = m.debug_stage(a, b, ffm.STAGE_SEEDS, dir=d).cpu().numpy()
+        assert np.array_equal(s, orc.seed_nn(D[d], D[1 - d], 3)), (kind, d)
+    m.close()
+
+
 @pytest.mark.parametrize("kind", ["kitti", "periodic"])
 def test_seed_search_full_resolution_sampled(torch, ffm, orc, kind):
     """Seed search over a whole 1242x375 level (levels = 1: Q = 51750 seeds
