@@ -213,10 +213,10 @@ def seednn_bench(torch, ff, pair, batch_prof):
     The tie-resolving pass that follows it (one chunk of 256 entries per seed)
     is reported beside it as resolve_us."""
     q, n = seed_counts(W0, H0, LEVELS)
-    launches, ms, nbatch = batch_prof
+    launches, ms, nbatch, resolve_us = batch_prof
     per_launch = nbatch * 2 * q * n * 16 * 2
     grouped = {"useful_tops": per_launch / (ms / launches * 1e-3) / 1e12, "avg_us": 1000.0 * ms / launches,
-               "resolve_us": batch_prof[3]}
+               "resolve_us": resolve_us}
     grouped["issued_tops"] = 4 * grouped["useful_tops"]
     m = ff.Matcher(levels=1, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
     a, b = pair

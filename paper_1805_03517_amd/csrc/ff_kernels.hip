@@ -692,8 +692,11 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     if (qbase >= Q) return;
     // Per seed: the best key over its 16 columns; splits merge (score, first
     // tile of the chunk) with a 64-bit atomicMax on (score + 2^20) << 32 |
-    // ~tile, so the merged key names the earliest chunk reaching the best
-    // score.  k_seed_resolve then finds the lowest index inside that chunk.
+    // low word, so the merged key names the earliest chunk reaching the best
+    // score.  Low word: (0xFFFF - tile) << 16 | the mask of columns reaching
+    // the key (a chunk lies in one split, so the mask never decides the max);
+    // with more than 65536 tiles, ~tile and every column.  k_seed_resolve then
+    // finds the lowest index inside that chunk.
 #pragma unroll
     for (int mq = 0; mq < MQ; ++mq)
 #pragma unroll
@@ -701,53 +704,58 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
             int k = best[mq][i];
 #pragma unroll
             for (int off = 1; off < 16; off <<= 1) k = max(k, __shfl_xor(k, off, 64));
+            const uint32_t cols = (uint32_t)(__ballot(best[mq][i] == k) >> (16 * g)) & 0xFFFFu;
             const int q = qbase + 16 * mq + 4 * g + i;
             if (m == 0 && q < Q && (k >> 11) != kNoScore) {
                 const uint32_t tb = (uint32_t)(t0 + (2047 - (k & 2047)) * kSeedChunk);
+                const uint32_t lo = ntiles > 65536 ? 0xFFFFFFFFu - tb : ((0xFFFFu - tb) << 16) | cols;
                 const unsigned long long key =
-                    ((unsigned long long)(uint32_t)((k >> 11) + (1 << 20)) << 32) | (unsigned long long)(0xFFFFFFFFu - tb);
+                    ((unsigned long long)(uint32_t)((k >> 11) + (1 << 20)) << 32) | (unsigned long long)lo;
                 atomicMax(&P.keys[dir][q], key);
             }
         }
 }
 
 // The lowest database index reaching each seed's best score: the merged key
-// holds the score and the first tile of the earliest chunk reaching it, so
-// the answer is the first of that chunk's 256 entries (16 tiles) with the
-// score, evaluated from the int8 descriptors as 2 a.b - |b|^2 with v_dot4 (the
-// integer the MFMA forms).  Entries past the chunk's split come later than
-// every entry of the chunk, so scanning all 16 tiles finds the same first
-// one.  The key's low word becomes ~index.  One wave per seed, four entries
-// per lane; grid (ceil(seeds / 4), 2 * pairs), 256 threads.
+// holds the score, the first tile of the earliest chunk reaching it and the
+// columns that reach it there, so the answer is the first of those columns'
+// entries in the chunk's 16 tiles with the score, evaluated from the int8
+// descriptors as 2 a.b - |b|^2 with v_dot4 (the integer the MFMA forms).
+// Entries past the chunk's split come later than every entry of the chunk,
+// so scanning all 16 tiles finds the same first one.  The key's low word
+// becomes ~index.  16 lanes per seed, lane t taking tile t of each listed
+// column in turn; grid (ceil(seeds / 16), 2 * pairs), 256 threads.
 __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict__ pairs, int level, int stride)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
     const LevelDev& L = P.lv[level];
     const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
-    const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= Q) return;                                          // wave-uniform
-    const unsigned long long key = P.keys[dir][q];
+    const int t = threadIdx.x & 15;                              // tile of the chunk
+    const int q = blockIdx.x * 16 + (threadIdx.x >> 4);          // 16 lanes per seed
+    const bool live = q < Q;
+    const unsigned long long key = live ? P.keys[dir][q] : 0ull;
     const int S = (int)(uint32_t)(key >> 32) - (1 << 20);
-    const uint32_t tb = 0xFFFFFFFFu - (uint32_t)key;
-    const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
-    const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
-    const int a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
-              a3 = (int)(ad.w ^ 0x80808080u);
-    gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
-    uint4 bd[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t n = tb * 16u + (uint32_t)(64 * c + lane);
-        bd[c] = n < (uint32_t)N ? load_desc(DBd, n) : make_uint4(0, 0, 0, 0);
+    const bool wide = (N + 15) / 16 > 65536;
+    const uint32_t tb = wide ? 0xFFFFFFFFu - (uint32_t)key : 0xFFFFu - (((uint32_t)key >> 16) & 0xFFFFu);
+    uint32_t cols = !live ? 0u : wide ? 0xFFFFu : (uint32_t)key & 0xFFFFu;
+    int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if (live) {
+        const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
+        const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
+        a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
+        a3 = (int)(ad.w ^ 0x80808080u);
     }
+    gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
     uint32_t nmin = 0xFFFFFFFFu;
-#pragma unroll
-    for (int c = 3; c >= 0; --c) {
-        const uint32_t n = tb * 16u + (uint32_t)(64 * c + lane);
-        const int b0 = (int)(bd[c].x ^ 0x80808080u), b1 = (int)(bd[c].y ^ 0x80808080u),
-                  b2 = (int)(bd[c].z ^ 0x80808080u), b3 = (int)(bd[c].w ^ 0x80808080u);
+    while (cols) {                                               // uniform within the seed's 16 lanes
+        const uint32_t j = (uint32_t)__builtin_ctz(cols);
+        cols &= cols - 1u;
+        const uint32_t n = (tb + (uint32_t)t) * 16u + j;
+        if (n >= (uint32_t)N) continue;
+        const uint4 bd = load_desc(DBd, n);
+        const int b0 = (int)(bd.x ^ 0x80808080u), b1 = (int)(bd.y ^ 0x80808080u), b2 = (int)(bd.z ^ 0x80808080u),
+                  b3 = (int)(bd.w ^ 0x80808080u);
         int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
         ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
         ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
@@ -756,11 +764,11 @@ __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict_
         bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
         bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
         bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
-        if (n < (uint32_t)N && 2 * ab - bb == S) nmin = n;
+        if (2 * ab - bb == S) nmin = min(nmin, n);
     }
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, off, 64));
-    if (lane == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
+    for (int off = 1; off < 16; off <<= 1) nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, off, 64));
+    if (live && t == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
 }
 
 // ----------------------------------------------------------- level init --
@@ -1542,7 +1550,7 @@ void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, 
 }
 void launch_seed_resolve(const PairDev* d, int npairs, int level, int stride, int maxQ, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 3) / 4, 2 * npairs), dim3(256), 0, st, d, level, stride);
+    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 15) / 16, 2 * npairs), dim3(256), 0, st, d, level, stride);
 }
 void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
 {

@@ -87,6 +87,43 @@ def test_served_results_equal_results_alone(torch, ffm, orc):
     served.close()
 
 
+@pytest.mark.parametrize("opts", [dict(sub_iters=1, sub_radius=2, sparse_min=4),
+                                  dict(cost="census", seed2=0xBEEF, fb_eps=7)],
+                         ids=["subpixel_sparse", "census_second_check"])
+def test_served_options_equal_results_alone(torch, ffm, orc, opts):
+    """Served with the options on (sub-pixel refinement and sparsification;
+    Census cost and the second check): every result equals the same pair
+    run alone, the first one also the oracle."""
+    pairs = _pairs(10, seed=41)
+    dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in pairs]
+    alone = ffm.Matcher(levels=3, **opts)
+    ref = []
+    for k, (a, b) in enumerate(dev):
+        say("alone", opts, k, tuple(a.shape))
+        ref.append(alone.match(a, b))
+    torch.cuda.synchronize()
+    served = ffm.Matcher(levels=3, **opts)
+    served.serve_config(lanes=2, lane_bytes=256 << 20)
+    outs = {}
+    say("served burst of 10", opts)
+    for k in range(10):
+        outs[k] = served.submit(dev[k][0], dev[k][1], tag=2000 + k)
+    done = _wait_all(served, list(range(10)))
+    assert sorted(done) == [2000 + k for k in range(10)]
+    for k in range(10):
+        for key in ref[k]:
+            assert torch.equal(ref[k][key], outs[k][key]), (k, key)
+    kw = dict(levels=3, fb_eps=opts.get("fb_eps", 1), sub_iters=opts.get("sub_iters", 0),
+              sub_radius=opts.get("sub_radius", 2))
+    if opts.get("cost") == "census":
+        kw.update(cost_kind=orc.COST_CENSUS, two_checks=1, seed2=opts["seed2"])
+    r = orc.match(pairs[0][0], pairs[0][1], orc.params(**kw))
+    for key in ("flow_f", "cost_f", "mask_f", "flow_b", "mask_b"):
+        assert np.array_equal(outs[0][key].cpu().numpy(), r[key]), key
+    alone.close()
+    served.close()
+
+
 def test_tiny_lane_workspace_queues_fifo(torch, ffm):
     pairs = _pairs(10, seed=32)
     dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in pairs]
