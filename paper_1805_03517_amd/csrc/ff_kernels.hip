@@ -182,6 +182,19 @@ __device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H
     }
 }
 
+// A sweep's predecessor values: every lane takes its lower (higher)
+// neighbour's v, lane 0 (63) takes edge -- DPP wave_shr:1 (wave_shl:1), a
+// register-to-register shift of the whole wave with the edge lane left at the
+// `old` operand, instead of a permute through LDS.
+__device__ __forceinline__ uint32_t lane_from_lower(uint32_t v, uint32_t edge)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_from_higher(uint32_t v, uint32_t edge)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x130, 0xF, 0xF, false);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4-word S-P network,
 // key advanced by the Weyl constants between rounds.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
@@ -944,14 +957,12 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 if (fwd) {
-                    const uint32_t up = (uint32_t)__shfl_up((int)h[c], 1, 64);
                     const uint32_t edge = c == 0 ? carry : (uint32_t)__builtin_amdgcn_readlane((int)h[c > 0 ? c - 1 : 0], 63);
-                    pred[c] = lane == 0 ? edge : up;
+                    pred[c] = lane_from_lower(h[c], edge);
                 } else {
-                    const uint32_t dn = (uint32_t)__shfl_down((int)h[c], 1, 64);
                     const uint32_t edge = c == CH - 1 ? carry
                                                       : (uint32_t)__builtin_amdgcn_readlane((int)h[c < CH - 1 ? c + 1 : c], 0);
-                    pred[c] = lane == 63 ? edge : dn;
+                    pred[c] = lane_from_higher(h[c], edge);
                 }
                 need[c] = hp[c] && pred[c] != lp[c];
                 anyn |= need[c];
@@ -1215,14 +1226,12 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     if (fwd) {
-                        const uint32_t up = (uint32_t)__shfl_up((int)h[c], 1, 64);
                         const uint32_t edge = c == 0 ? carry : (uint32_t)__builtin_amdgcn_readlane((int)h[c > 0 ? c - 1 : 0], 63);
-                        pred[c] = lane == 0 ? edge : up;
+                        pred[c] = lane_from_lower(h[c], edge);
                     } else {
-                        const uint32_t dn = (uint32_t)__shfl_down((int)h[c], 1, 64);
                         const uint32_t edge = c == CH - 1 ? carry
                                                           : (uint32_t)__builtin_amdgcn_readlane((int)h[c < CH - 1 ? c + 1 : c], 0);
-                        pred[c] = lane == 63 ? edge : dn;
+                        pred[c] = lane_from_higher(h[c], edge);
                     }
                     need[c] = hp[c] && pred[c] != lp[c];
                     anyn |= need[c];
@@ -1587,9 +1596,10 @@ bool line_cross_write(int wpb, int maxlen)
     return (size_t)wpb * (size_t)maxlen * kLdsBytesPerPx <= 65536;
 }
 
-// Pixels of a row held in LDS: as many whole windows as let the 24 waves
-// per CU that the line kernels' registers allow share the CU's 160 KiB of LDS;
-// the rest of a longer row goes through global memory between the passes.
+// Pixels of a row held in LDS: as many whole windows as let 24 waves per CU
+// share the CU's 160 KiB of LDS (sizing for the 28 that the registers allow
+// measured slower: more of each row goes through global memory); the rest of
+// a longer row goes through global memory between the passes.
 template <int CH, int WPB>
 int row_lds_pixels(int maxlen)
 {
