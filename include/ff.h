@@ -79,19 +79,22 @@ typedef enum {
                                ax ay over the biased bytes, (sum + 8) >> 4); flow
                                outputs then in quarter pixels, fberr in 1/16 px^2,
                                the consistency target rounded half up to whole
-                               pixels; descriptor cost only; W, H <= 2048         */
+                               pixels; descriptor cost only; W, H <= 2048; the
+                               refinement runs a fixed schedule ((1, 8, 0) rows,
+                               (1, 4, 0) columns) whatever the tuning            */
 
 /* Search parameters (Sec. 3.1; Table 3 gives epsilon = 1 and s = 7 for
  * KITTI, epsilon = 7 and s = 4 for MPI Sintel). */
 typedef struct {
     int32_t  levels;        /* pyramid levels L, 1..8 (3 or 4 in the workloads)  */
-    int32_t  seed_stride;   /* seed grid step at the coarsest level (3)          */
-    int32_t  iters;         /* iterations per level (2)                          */
+    int32_t  seed_stride;   /* seed grid step at the coarsest level, 1..64 (3)   */
+    int32_t  iters;         /* iterations per level, 0..64 (2)                   */
     int32_t  rs_radius;     /* random-search radius R, 0..1024 (16)              */
     int32_t  fb_eps;        /* consistency threshold in px, 0..1024 (1)          */
     uint64_t seed;          /* random-search key                                 */
     uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
-    uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK, or 0 */
+    uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK |
+                               FF_SUBPIXEL, or 0                               */
     int32_t  sparse_min;    /* s: matches a 3x3 block needs to keep one, 1..9
                                (7); read only with FF_SPARSIFY                 */
     uint64_t seed2;         /* random-search key of the second search; read
@@ -128,7 +131,9 @@ typedef struct {
     uint8_t* sparse_bwd;
 } ff_pair;
 
-/* Create a handle on HIP device `device` (must be gfx950).  Copies *params. */
+/* Create a handle on HIP device `device` (must be gfx950).  Copies *params;
+ * FF_ERR_INVALID for a parameter outside the ranges above, an unknown flag,
+ * or FF_SUBPIXEL together with FF_COST_CENSUS. */
 ff_status ff_create(const ff_params* params, int device, ff_handle* out);
 
 /* Match one pair (the whole search above) on `stream`. */
@@ -136,7 +141,7 @@ ff_status ff_match_pair(ff_handle h, const ff_pair* pair, void* stream);
 
 /* Match n independent pairs, of any sizes, in one grouped pass: every stage
  * runs once over all pairs.  Outputs are bit-identical to n calls of
- * ff_match_pair.  n >= 1. */
+ * ff_match_pair.  1 <= n <= 32767. */
 ff_status ff_match_batch(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
 
 /* Synchronise the handle's device and free everything it owns. */
@@ -163,8 +168,8 @@ uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
  * outputs are complete.  ff_match_pair / ff_match_batch on the same handle
  * use a separate workspace.
  *
- * ff_serve_config: (re)configure; FF_ERR_BUSY while requests are queued or
- *   running.  Without it the first ff_submit configures 4 lanes of
+ * ff_serve_config: (re)configure, 1 <= lanes <= 16, lane_bytes >= 1 MiB;
+ *   FF_ERR_BUSY while requests are queued or running.  Without it the first ff_submit configures 4 lanes of
  *   hbm_budget / 4 bytes (4 GiB each when no budget is set).
  * ff_submit: FF_ERR_BUDGET when the pair alone exceeds lane_bytes.
  * ff_poll: non-blocking; writes up to `max` finished tags (completion
