@@ -410,14 +410,18 @@ def test_invalid_arguments_are_rejected(torch, ffm):
     tight.close()
 
 
-def test_graph_replays_match_direct_launches(torch, ffm, orc, monkeypatch):
+@pytest.mark.parametrize("opts", [{}, dict(sub_iters=2, sub_radius=3, sparse_min=5),
+                                  dict(cost="census", seed2=0xBEEF, fb_eps=3, sparse_min=4)],
+                         ids=["plain", "subpixel_sparse", "census_second_check_sparse"])
+def test_graph_replays_match_direct_launches(torch, ffm, orc, monkeypatch, opts):
     """The second call with a geometry is captured into a hipGraph and later
     calls replay it with a freshly uploaded pair table.  Every replay, with
-    eager work and synchronisation in between, must equal direct launches."""
+    eager work and synchronisation in between, must equal direct launches,
+    with every option flag as well."""
     monkeypatch.setenv("FF_GRAPHS", "0")
-    direct = ffm.Matcher(levels=3)
+    direct = ffm.Matcher(levels=3, **opts)
     monkeypatch.setenv("FF_GRAPHS", "1")
-    graphed = ffm.Matcher(levels=3)
+    graphed = ffm.Matcher(levels=3, **opts)
     sets = []
     for s in range(3):
         pairs = [synth.translated_pair(np.random.default_rng([40, s, k]), 150 + 7 * k, 90 + 5 * k,
@@ -425,7 +429,7 @@ def test_graph_replays_match_direct_launches(torch, ffm, orc, monkeypatch):
         sets.append([(_dev(torch, a), _dev(torch, b)) for a, b in pairs])
     for rep in range(6):
         dev = sets[rep % 3]
-        say("graph replay", rep)
+        say("graph replay", opts, rep)
         g = graphed.match_batch(dev)
         scratch = torch.randn(1 << 20, device="cuda").sum()       # eager work between replays
         torch.cuda.synchronize()
