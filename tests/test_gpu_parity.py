@@ -159,6 +159,10 @@ EDGE_CASES = [
     (8192, 8, 1, 4, 3, 16, 1, 1),      # maximum width
     (6, 8192, 1, 2, 3, 3, 1, 1),       # maximum height, runtime radius
     (97, 71, 3, 3, 4, 2, 1, 0),        # zero iterations: init only
+    (512, 384, 1, 8, 3, 16, 1, 1),     # maximum levels: coarsest 4x3
+    (100, 80, 3, 2, 64, 1024, 1024, 1),  # maximum stride, radius (11 trials) and eps
+    (40, 30, 1, 2, 3, 4, 1, 64),       # maximum iterations
+    (2000, 40, 1, 3, 3, 16, 1, 2),     # rows longer than the LDS-held part: first windows via global memory
 ]
 
 
