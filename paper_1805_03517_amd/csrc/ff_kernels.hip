@@ -1058,7 +1058,6 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                                                          int iter, int upto, SearchConst sc, int xw, int finit)
 {
     static_assert(!STG || CK == 0, "the staged random search holds descriptors");
-    static_assert(CK != 2 || RC == 0, "the sub-pixel refinement runs the generic pass");
     const uint32_t rlev = sc.rng_level >= 0 ? (uint32_t)sc.rng_level : (uint32_t)level;   // Philox level word
     using FT = typename Feat<CK>::T;
     constexpr size_t FB = CK == 1 ? 8 : 16;                      // feature bytes per pixel
@@ -1137,7 +1136,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const bool lout = xwk && (COL || (fwd && upto >= 2));
         const bool quarter = CK == 2 && !COL && fwd && finit;
 
-        if constexpr (!STG && RC > 0 && CH <= 2) {
+        if constexpr (!STG && RC > 0 && CH <= 2 && CK != 2) {      // the sub-pixel refinement: generic pass
             if (active)
                 line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
                                                  (uint32_t)level, ctr2, sc, P, dir,
@@ -1628,10 +1627,14 @@ bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int 
         launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st); \
         return true;                                                                                 \
     }
-    FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
-    FF_LINE_CASE(2, 2, 0) FF_LINE_CASE(2, 4, 0) FF_LINE_CASE(2, 8, 0)
-    FF_LINE_CASE(4, 2, 0) FF_LINE_CASE(4, 4, 0) FF_LINE_CASE(4, 8, 0)
-    FF_LINE_CASE(8, 2, 0) FF_LINE_CASE(8, 4, 0) FF_LINE_CASE(8, 8, 0)
+    if constexpr (CK == 2) {                                     // the refinement's fixed schedule
+        FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
+    } else {
+        FF_LINE_CASE(1, 2, 0) FF_LINE_CASE(1, 4, 0) FF_LINE_CASE(1, 8, 0)
+        FF_LINE_CASE(2, 2, 0) FF_LINE_CASE(2, 4, 0) FF_LINE_CASE(2, 8, 0)
+        FF_LINE_CASE(4, 2, 0) FF_LINE_CASE(4, 4, 0) FF_LINE_CASE(4, 8, 0)
+        FF_LINE_CASE(8, 2, 0) FF_LINE_CASE(8, 4, 0) FF_LINE_CASE(8, 8, 0)
+    }
     if constexpr (CK == 0) {
         FF_LINE_CASE(1, 4, 1) FF_LINE_CASE(1, 8, 1) FF_LINE_CASE(1, 16, 1) FF_LINE_CASE(2, 8, 1)
     }
@@ -1643,25 +1646,35 @@ template <int CK>
 bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
                     int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
 {
-    if constexpr (CK != 2) {
+    if constexpr (CK == 2) {
+        // the refinement: radius 2 (two trials) unrolled, so both trials'
+        // neighbourhood loads are in flight together; other radii in a loop
+        if (sc.radius == 2)
+            return col ? launch_line_rc<2, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+                       : launch_line_rc<2, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
+                                                      finit, st);
+        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+                   : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit,
+                                                  st);
+    } else {
         if (sc.radius == 16)
             return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0,
                                                       st)
                        : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
                                                        finit, st);
+        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+                   : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
     }
-    return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
-               : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
-                                              CK == 2 ? finit : 0, st);
 }
 
 // One row or column phase of every pair and direction at one level.  ch =
 // chunks of 64 px per relaxation window, wpb = lines per block, stg = staged
 // random search, ck = cost (0 descriptor SAD, 1 Census, 2 sub-pixel SAD on
-// quarter-pixel flows, generic pass only); supported: stg 0
-// with ch in {1, 2, 4, 8} and wpb in {2, 4, 8} (ch <= 2 runs the
-// software-pipelined pass at radius 16); stg 1, descriptor cost only, with
-// (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false otherwise.
+// quarter-pixel flows: generic pass, (ch, wpb) in {(1, 4), (1, 8)} only);
+// supported: stg 0 with ch in {1, 2, 4, 8} and wpb in {2, 4, 8} (ch <= 2
+// runs the software-pipelined pass at radius 16); stg 1, descriptor cost
+// only, with (ch, wpb) in {(1, 4), (1, 8), (1, 16), (2, 8)}.  Returns false
+// otherwise.
 // nlines / maxlen: the batch's largest line count and line length.  The
 // column phase reads the row-major state and, when line_cross_write()
 // allows it, also writes it (otherwise its result stays in stateT).
