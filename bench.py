@@ -407,6 +407,22 @@ def c4_bench(torch, ff, n_pairs):
         mb.match_batch(dev, outs=ob)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    # seed search of the batch on i8 MFMA: one grouped launch over all pairs
+    mb.profile(True)
+    mb.match_batch(dev, outs=ob)
+    prof = mb.profile_read()
+    mb.profile(False)
+    useful = 0
+    for a, _, _ in pairs:
+        wc, hc = a.shape[1] >> 2, a.shape[0] >> 2              # coarsest of 3 levels
+        useful += 2 * (-(-wc // 3)) * (-(-hc // 3)) * wc * hc * 16 * 2
+    sn, sms = prof["seed_nn"]
+    rn, rms = prof["seed_resolve"]
+    seed = {"avg_us": 1000.0 * sms / sn, "resolve_us": 1000.0 * rms / rn,
+            "useful_tops": useful / (sms / sn * 1e-3) / 1e12}
+    seed["issued_tops"] = 4 * seed["useful_tops"]
+    seed["useful_frac"] = seed["useful_tops"] / I8_PEAK_TOPS
+    seed["issued_frac"] = seed["issued_tops"] / I8_PEAK_TOPS
     for (a, b), o in zip(dev, op):              # warm the per-pair path (graphs per shape)
         mp.match(a, b, out=o)
     torch.cuda.synchronize()
@@ -420,7 +436,7 @@ def c4_bench(torch, ff, n_pairs):
     mp.close()
     return {"pairs": n_pairs, "batched": {"pairs_per_s": n_pairs / tb, "px_per_s": px / tb, "ms": 1000 * tb},
             "per_pair": {"pairs_per_s": n_pairs / tp, "px_per_s": px / tp, "ms": 1000 * tp},
-            "bit_identical": bool(same), "schedule": tuning}
+            "bit_identical": bool(same), "schedule": tuning, "seed_nn": seed}
 
 
 def main():

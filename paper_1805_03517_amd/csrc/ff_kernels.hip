@@ -736,16 +736,17 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 // descriptors as 2 a.b - |b|^2 with v_dot4 (the integer the MFMA forms).
 // Entries past the chunk's split come later than every entry of the chunk,
 // so scanning all 16 tiles finds the same first one.  The key's low word
-// becomes ~index.  16 lanes per seed, lane t taking tile t of each listed
-// column in turn; grid (ceil(seeds / 16), 2 * pairs), 256 threads.
+// becomes ~index.  4 lanes per seed, lane s taking tiles 4s .. 4s+3 of each
+// listed column in turn (64 seeds a block, so small pairs of a big batch
+// need few blocks); grid (ceil(seeds / 64), 2 * pairs), 256 threads.
 __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict__ pairs, int level, int stride)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int dir = blockIdx.y & 1;
     const LevelDev& L = P.lv[level];
     const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
-    const int t = threadIdx.x & 15;                              // tile of the chunk
-    const int q = blockIdx.x * 16 + (threadIdx.x >> 4);          // 16 lanes per seed
+    const int sub = threadIdx.x & 3;                             // tiles 4 sub .. 4 sub + 3 of the chunk
+    const int q = blockIdx.x * 64 + (threadIdx.x >> 2);          // 4 lanes per seed
     const bool live = q < Q;
     const unsigned long long key = live ? P.keys[dir][q] : 0ull;
     const int S = (int)(uint32_t)(key >> 32) - (1 << 20);
@@ -761,27 +762,34 @@ __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict_
     }
     gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
     uint32_t nmin = 0xFFFFFFFFu;
-    while (cols) {                                               // uniform within the seed's 16 lanes
+    while (cols) {                                               // uniform within the seed's 4 lanes
         const uint32_t j = (uint32_t)__builtin_ctz(cols);
         cols &= cols - 1u;
-        const uint32_t n = (tb + (uint32_t)t) * 16u + j;
-        if (n >= (uint32_t)N) continue;
-        const uint4 bd = load_desc(DBd, n);
-        const int b0 = (int)(bd.x ^ 0x80808080u), b1 = (int)(bd.y ^ 0x80808080u), b2 = (int)(bd.z ^ 0x80808080u),
-                  b3 = (int)(bd.w ^ 0x80808080u);
-        int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
-        ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
-        ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
-        ab = __builtin_amdgcn_sdot4(a3, b3, ab, false);
-        int bb = __builtin_amdgcn_sdot4(b0, b0, 0, false);
-        bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
-        bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
-        bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
-        if (2 * ab - bb == S) nmin = min(nmin, n);
-    }
+        uint4 bd[4];                                             // the lane's four tiles: loads in flight together
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, off, 64));
-    if (live && t == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
+            bd[k] = n < (uint32_t)N ? load_desc(DBd, n) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
+            const int b0 = (int)(bd[k].x ^ 0x80808080u), b1 = (int)(bd[k].y ^ 0x80808080u),
+                      b2 = (int)(bd[k].z ^ 0x80808080u), b3 = (int)(bd[k].w ^ 0x80808080u);
+            int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
+            ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
+            ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
+            ab = __builtin_amdgcn_sdot4(a3, b3, ab, false);
+            int bb = __builtin_amdgcn_sdot4(b0, b0, 0, false);
+            bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
+            bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
+            bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
+            if (n < (uint32_t)N && 2 * ab - bb == S) nmin = min(nmin, n);
+        }
+    }
+    nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 1, 64));
+    nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 2, 64));
+    if (live && sub == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
 }
 
 // ----------------------------------------------------------- level init --
@@ -1558,7 +1566,7 @@ void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, 
 }
 void launch_seed_resolve(const PairDev* d, int npairs, int level, int stride, int maxQ, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 15) / 16, 2 * npairs), dim3(256), 0, st, d, level, stride);
+    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 63) / 64, 2 * npairs), dim3(256), 0, st, d, level, stride);
 }
 void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
 {
