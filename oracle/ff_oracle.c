@@ -6,12 +6,12 @@
  *
  * The method (FlowFields++, Sec. 3.1 "Matches"): matching cost is a distance
  * between feature descriptors; initial matches come from Walsh-Hadamard
- * descriptors matched at the lowest resolution; they are propagated into all
- * four directions for a number of iterations at each scale of a
- * coarse-to-fine pyramid, with a random search (a small random offset added
- * to each flow component) after the last three propagation steps of every
- * iteration; a forward-backward consistency check with threshold epsilon
- * (Table 3: epsilon = 1 for KITTI) removes outliers.
+ * descriptors matched at the lowest resolution; propagation then spreads them
+ * in four directions, several iterations per pyramid level from coarse to
+ * fine, and a random search perturbs both flow components slightly after
+ * each of an iteration's last three propagation steps; a forward-backward
+ * consistency check with threshold epsilon (Table 3: epsilon = 1 for KITTI)
+ * removes outliers.
  *
  * The paper leaves the exact arithmetic to the Flow Fields papers it cites.
  * The readings taken here (integer luma, 2x2 box pyramid, K = 16 sequency
@@ -44,7 +44,7 @@ void ffo_gray(const uint8_t* img, int W, int H, int C, uint8_t* gray)
 }
 
 /* ------------------------------------------------------------- pyramid -- */
-/* "each scale" of the coarse-to-fine search (Sec. 3.1): factor-2 levels,
+/* The scales of the coarse-to-fine search (Sec. 3.1): factor-2 levels,
  * 2x2 box mean rounded half up, odd trailing row/column dropped.          */
 void ffo_down2(const uint8_t* src, int W, int H, uint8_t* dst)
 {
@@ -267,7 +267,7 @@ void ffo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* --------------------------------------------------------- propagation -- */
-/* Propagation "into all four quadrants" (Sec. 3.1), read as four scanline
+/* Propagation in four directions (Sec. 3.1), read as four scanline
  * sweeps per iteration.  Within a sweep, pixels are visited in scan order;
  * each pixel compares its own flow with the flow its predecessor on the
  * line holds after that predecessor was visited, and takes the
@@ -312,8 +312,8 @@ void ffo_sweep_census(const uint64_t* CA, const uint64_t* CB, int W, int H, int 
 }
 
 /* ------------------------------------------------------- random search -- */
-/* Random search (Sec. 3.1): a small random offset is added to each flow
- * component.  Reading: per pixel, J = floor(log2 R) + 1 trials with radius
+/* Random search (Sec. 3.1): both flow components are perturbed by a small
+ * random amount.  Reading: per pixel, J = floor(log2 R) + 1 trials with radius
  * r_j = R >> j around the flow v0 the pixel held before the pass; offsets
  * are uniform integers in [-r_j, r_j] (taken as u mod (2 r_j + 1) - r_j of
  * a Philox word); a trial replaces the current best only when its flow

@@ -117,8 +117,8 @@ void ffo_fb_error(int W, int H, const int16_t* F, const int32_t* cF,
 void ffo_fb_error_u(int W, int H, int unit, const int16_t* F, const int32_t* cF,
                     const int16_t* B, const int32_t* cB, int32_t* err);
 
-/* Two consistency checks (Sec. 3.1): F against two inverse fields B1 and B2
- * computed with different matching parameters.  err = the larger of the two
+/* Two consistency checks (Sec. 3.1): F against two inverse fields B1 and B2,
+ * the second matched with other parameters.  err = the larger of the two
  * errors (FFO_INF when either is); a match passes both checks exactly when
  * err <= eps^2.                                                            */
 void ffo_fb_error2(int W, int H, const int16_t* F, const int32_t* cF, const int16_t* B1, const int32_t* cB1,

@@ -211,8 +211,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Random search of one pixel (Sec. 3.1: a small random offset added to each
-// flow component).  Trials j = 0..J-1 with radius R >> j around the pre-pass
+// Random search of one pixel (Sec. 3.1: both flow components perturbed by a
+// small random amount).  Trials j = 0..J-1 with radius R >> j around the pre-pass
 // flow v0; offsets come from the Philox block at counter
 // (y*W + x, level, iter << 2 | pass, j >> 1), words (0,1) for even j and
 // (2,3) for odd j.  All trial costs are gathered first (independent loads),

@@ -1,5 +1,5 @@
-"""Second consistency check (Sec. 3.1: two checks against inverse fields
-computed with different matching parameters -- here the same search keyed
+"""Second consistency check (Sec. 3.1: a match is also checked against an
+inverse field matched with other parameters -- here the same search keyed
 by seed2) through the C ABI, bit-exact against the oracle, alone and with
 the Census cost and sparsification.  Each GPU step prints its case first."""
 import numpy as np
