@@ -39,23 +39,24 @@ typedef FF_GLOBAL i32x2 gi2;
 // One line's search state in LDS between a phase's passes: flows as u32 and
 // costs as u16 in two planes (6 bytes a pixel instead of 8, so more lines fit
 // per CU).  Every finite cost fits: SAD of 16 bytes <= 4080, Hamming <= 48;
-// INF is stored as 0xFFFF.  Pixels from lo on are held here; a long row keeps
-// its first windows (p < lo) in global memory instead, so that LDS does not
-// cap the number of waves per CU.
+// INF is stored as 0xFFFF.  Pixels below hi are held here; a long row keeps
+// its last windows (p >= hi) in global memory instead, so that LDS does not
+// cap the number of waves per CU -- the first pass writes them last and the
+// second pass (right to left) reads them first, while they are still in L2.
 struct LdsLine {
     __attribute__((address_space(3))) uint32_t* f;
     __attribute__((address_space(3))) uint16_t* c;
-    int lo;
-    __device__ __forceinline__ bool has(int p) const { return p >= lo; }
+    int hi;
+    __device__ __forceinline__ bool has(int p) const { return p < hi; }
     __device__ __forceinline__ i32x2 get(int p) const
     {
-        const uint32_t cc = c[p - lo];
-        return i32x2{(int)f[p - lo], cc == 0xFFFFu ? kInf : (int)cc};
+        const uint32_t cc = c[p];
+        return i32x2{(int)f[p], cc == 0xFFFFu ? kInf : (int)cc};
     }
     __device__ __forceinline__ void set(int p, i32x2 v) const
     {
-        f[p - lo] = (uint32_t)v.x;
-        c[p - lo] = (uint16_t)(v.y == kInf ? 0xFFFFu : (uint32_t)v.y);
+        f[p] = (uint32_t)v.x;
+        c[p] = (uint16_t)(v.y == kInf ? 0xFFFFu : (uint32_t)v.y);
     }
 };
 
@@ -1088,7 +1089,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     // in place and the passes write stateT).  Row phase: the first pass reads
     // the state from global memory and leaves its result in LDS, the second
     // pass reads it there and writes global memory; a row longer than xw
-    // keeps its first windows in global memory between the passes.
+    // keeps its last windows in global memory between the passes.
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
@@ -1106,10 +1107,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     __shared__ int sample[2][WPB][2];                            // per parity: a flow sample (i, j) per line
     __shared__ int sample_ok[2][WPB];
     extern __shared__ uint32_t lbuf_[];                          // xw: WPB lines x xw pixels, two planes
-    const int lo = (!COL && len > xw) ? (len - xw + WIN - 1) / WIN * WIN : 0;
+    const int hi = (!COL && len > xw) ? xw / WIN * WIN : len;  // whole windows in LDS
     auto line_lds = [&](int k) {
         __attribute__((address_space(3))) uint32_t* const f = (__attribute__((address_space(3))) uint32_t*)lbuf_;
-        return LdsLine{f + k * xw, (__attribute__((address_space(3))) uint16_t*)(f + WPB * xw) + k * xw, lo};
+        return LdsLine{f + k * xw, (__attribute__((address_space(3))) uint16_t*)(f + WPB * xw) + k * xw, hi};
     };
     const LdsLine lline = line_lds(wave);
     if (xwc) {
