@@ -1,0 +1,118 @@
+"""Seeded sweep over the parameter space through the C ABI against the
+oracle: random sizes (ragged, thin, tiny), channels, levels, seed stride,
+random-search radius, threshold, iteration count, schedules and every
+combination of the option flags (Census cost, second consistency check,
+sparsification, quarter-pixel refinement), bit for bit.  The cases are
+fixed by a seed, so a failure names a reproducible case; each GPU step
+prints it first."""
+import numpy as np
+import pytest
+
+from paper_1805_03517_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU test run without a visible GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ffm():
+    from paper_1805_03517_amd import ff
+    return ff
+
+
+SCHEDULES = [None, "generic", "pipelined", "narrow", "staged"]
+
+
+def _cases(n=64, seed=2024):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        W = int(rng.choice([int(rng.integers(1, 40)), int(rng.integers(40, 330))]))
+        H = int(rng.choice([int(rng.integers(1, 40)), int(rng.integers(40, 250))]))
+        lv_max = 1
+        while lv_max < 6 and (W >> lv_max) >= 1 and (H >> lv_max) >= 1:
+            lv_max += 1
+        census = bool(rng.integers(0, 2))
+        sub = (not census) and bool(rng.integers(0, 2))
+        out.append(dict(
+            W=W, H=H, C=int(rng.choice([1, 3])), levels=int(rng.integers(1, lv_max + 1)),
+            stride=int(rng.integers(1, 7)), R=int(rng.choice([0, 1, 3, 7, 16, 40])),
+            eps=int(rng.integers(0, 6)), iters=int(rng.integers(0, 4)),
+            census=census, second=bool(rng.integers(0, 2)), s=int(rng.choice([0, 0, 1, 4, 9])),
+            sub=sub, sub_iters=int(rng.integers(1, 3)), sub_radius=int(rng.choice([0, 1, 2, 5])),
+            sched=SCHEDULES[int(rng.integers(0, len(SCHEDULES) - (1 if census else 0)))], d=(int(rng.integers(-9, 10)), int(rng.integers(-9, 10))),
+            img_seed=1000 + k))
+    return out
+
+
+CASES = _cases()
+
+
+def _images(c):
+    rng = np.random.default_rng(c["img_seed"])
+    W, H = c["W"], c["H"]
+    if c["C"] == 1:
+        i1, i2, _ = synth.translated_pair(rng, W, H, d=c["d"], rect=(min(12, W // 2), min(9, H // 2)), rect_d=(2, -3))
+        return i1, i2
+    ch = [synth.translated_pair(np.random.default_rng([c["img_seed"], j]), W, H, d=c["d"], rect=(0, 0)) for j in range(3)]
+    return np.stack([x[0] for x in ch], -1), np.stack([x[1] for x in ch], -1)
+
+
+def _schedule(name, L):
+    if name is None:
+        return None
+    return {"generic": [4, 4, 0] * L + [4, 4, 0] * L, "pipelined": [1, 8, 0] * L + [2, 4, 0] * L,
+            "narrow": [1, 2, 0] * L + [2, 2, 0] * L, "staged": [1, 8, 1] * L + [2, 8, 1] * L}[name]
+
+
+@pytest.mark.parametrize("c", CASES, ids=[f"case{k}" for k in range(len(CASES))])
+def test_random_configuration(torch, ffm, orc, c):
+    i1, i2 = _images(c)
+    seed2 = 0xC0DE if c["second"] else None
+    kw = dict(levels=c["levels"], seed_stride=c["stride"], iters=c["iters"], rs_radius=c["R"], fb_eps=c["eps"],
+              seed=0x5EED, cost_kind=orc.COST_CENSUS if c["census"] else orc.COST_WH,
+              two_checks=1 if c["second"] else 0, seed2=seed2 or 0,
+              sub_iters=c["sub_iters"] if c["sub"] else 0, sub_radius=c["sub_radius"])
+    say("random configuration", c)
+    m = ffm.Matcher(levels=c["levels"], seed_stride=c["stride"], iters=c["iters"], rs_radius=c["R"],
+                    fb_eps=c["eps"], seed=0x5EED, cost="census" if c["census"] else "wh", seed2=seed2,
+                    sparse_min=c["s"], sub_iters=c["sub_iters"] if c["sub"] else 0, sub_radius=c["sub_radius"])
+    sched = _schedule(c["sched"], c["levels"])
+    if sched is not None:
+        m.set_tuning(sched)
+    out = m._outputs(c["H"], c["W"])
+    out.setdefault("fberr_f", torch.empty((c["H"], c["W"]), dtype=torch.int32, device="cuda"))
+    out.setdefault("fberr_b", torch.empty((c["H"], c["W"]), dtype=torch.int32, device="cuda"))
+    got = m.match(torch.from_numpy(np.ascontiguousarray(i1)).cuda(), torch.from_numpy(np.ascontiguousarray(i2)).cuda(),
+                  out=out)
+    torch.cuda.synchronize()
+    ref = orc.match(i1, i2, orc.params(**kw))
+    unit = 4 if c["sub"] else 1
+    if c["second"]:
+        alt = orc.match(i1, i2, orc.params(**{**kw, "two_checks": 0, "seed": seed2}))
+        ref["fberr_f"] = orc.fb_error2(ref["flow_f"], ref["cost_f"], ref["flow_b"], ref["cost_b"], alt["flow_b"],
+                                       alt["cost_b"], unit=unit)
+        ref["fberr_b"] = orc.fb_error2(ref["flow_b"], ref["cost_b"], ref["flow_f"], ref["cost_f"], alt["flow_f"],
+                                       alt["cost_f"], unit=unit)
+    else:
+        ref["fberr_f"] = orc.fb_error(ref["flow_f"], ref["cost_f"], ref["flow_b"], ref["cost_b"], unit=unit)
+        ref["fberr_b"] = orc.fb_error(ref["flow_b"], ref["cost_b"], ref["flow_f"], ref["cost_f"], unit=unit)
+    if c["s"]:
+        ref["sparse_f"] = orc.sparsify(ref["mask_f"], ref["fberr_f"], c["s"])
+        ref["sparse_b"] = orc.sparsify(ref["mask_b"], ref["fberr_b"], c["s"])
+    for k in ref:
+        g = got[k].cpu().numpy()
+        if not np.array_equal(g, ref[k]):
+            bad = np.argwhere(g != ref[k])
+            raise AssertionError(f"{c}: {k} differs at {len(bad)} places, first {bad[:3].tolist()}")
+    m.close()
