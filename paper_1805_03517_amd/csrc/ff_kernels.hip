@@ -76,6 +76,28 @@ __device__ __forceinline__ int32_t sad16(uint4 a, uint4 b)
     return (int32_t)s;
 }
 
+// Blocks are dispatched to the 8 XCDs round-robin by linear block id; the
+// remap gives each XCD a contiguous range of logical blocks.  Line phases:
+// the lines of one pair and direction (which gather from the same descriptor
+// plane) run on one XCD and share its L2.  Tiled kernels: neighbouring tiles
+// run on one XCD, so the cache lines their edges share are completed in one
+// L2 before they are written back.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+// Logical (x, y, z) block of a 3-D grid under xcd_remap.
+__device__ __forceinline__ int3 xcd_block3()
+{
+    const int nxy = gridDim.x * gridDim.y;
+    const int lb = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y + nxy * blockIdx.z, nxy * gridDim.z);
+    const int z = lb / nxy, r = lb - z * nxy;
+    return make_int3(r % gridDim.x, r / gridDim.x, z);
+}
+
 // Index of pixel (x, y) in a row-major ([H][W]) or column-major ([W][H]) plane.
 template <bool COL>
 __device__ __forceinline__ size_t pix(int x, int y, int W, int H)
@@ -357,11 +379,12 @@ __device__ __forceinline__ uint32_t desc_word(s16x2 lo, s16x2 hi, uint32_t bias)
 
 __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs, int level)
 {
-    const PairDev& P = pairs[blockIdx.z >> 1];
-    const int img = blockIdx.z & 1;
+    const int3 tb = xcd_block3();
+    const PairDev& P = pairs[tb.z >> 1];
+    const int img = tb.z & 1;
     const LevelDev& L = P.lv[level];
     const int W = L.W, H = L.H;
-    const int x0 = blockIdx.x * kDescTX, y0 = blockIdx.y * kDescTY;
+    const int x0 = tb.x * kDescTX, y0 = tb.y * kDescTY;
     if (x0 >= W || y0 >= H) return;
     constexpr int TR = kDescTY + 7;                              // input rows
     __shared__ union {
@@ -427,14 +450,16 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
         out[i] = make_uint4(desc_word(al + bl, ah + bh, 0x80808000u), desc_word(al - bl, ah - bh, 0x80808080u),
                             desc_word(dl - el, dh - eh, 0x80808080u), desc_word(dl + el, dh + eh, 0x80808080u));
     }
+    // global (not flat) stores: a flat store also counts against the LDS
+    // wait counter, so every LDS wait and barrier below would wait for it
     const int x = x0 + c;
-    uint8_t* dst = L.desc[img];
+    FF_GLOBAL u32x4* dst = (FF_GLOBAL u32x4*)L.desc[img];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
         const int y = y0 + 8 * g + i;
-        if (x < W && y < H) *reinterpret_cast<uint4*>(dst + ((size_t)y * W + x) * 16) = out[i];
+        if (x < W && y < H) dst[(uint32_t)y * (uint32_t)W + (uint32_t)x] = u32x4{out[i].x, out[i].y, out[i].z, out[i].w};
     }
-    uint8_t* dstT = L.descT[img];
+    FF_GLOBAL u32x4* dstT = (FF_GLOBAL u32x4*)L.descT[img];
     for (int half = 0; half < 2; ++half) {                       // column-major, 16 rows at a time
         __syncthreads();                                         // row transforms / previous half consumed
         if ((g >> 1) == half) {
@@ -447,7 +472,10 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
             const int i = threadIdx.x + 256 * k;
             const int r = i % 16, cc = i / 16;
             const int xx = x0 + cc, yy = y0 + 16 * half + r;
-            if (xx < W && yy < H) *reinterpret_cast<uint4*>(dstT + ((size_t)xx * H + yy) * 16) = sm.res[r][cc];
+            if (xx < W && yy < H) {
+                const uint4 w = sm.res[r][cc];
+                dstT[(uint32_t)xx * (uint32_t)H + (uint32_t)yy] = u32x4{w.x, w.y, w.z, w.w};
+            }
         }
     }
 }
@@ -563,7 +591,7 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
     const LevelDev& L = P.lv[level];
     const int N = L.W * L.H;
     const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n < P.nsx * P.nsy) P.keys[img][n] = 0ull;
+    if (n < P.nsx * P.nsy) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
     if (n >= N) return;
     const uint4 db = load_desc((gcu8*)L.desc[img], n);
     const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
@@ -586,11 +614,11 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
         beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
     }
     beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
-    uint4* rec = reinterpret_cast<uint4*>(P.dbrec[img] + (size_t)n * 64);
-    rec[0] = b;
-    rec[1] = b;
-    rec[2] = make_uint4(beta[0], beta[1], beta[2], beta[3]);
-    rec[3] = make_uint4(beta[4], beta[5], beta[6], beta[7]);
+    FF_GLOBAL u32x4* rec = (FF_GLOBAL u32x4*)(P.dbrec[img] + (size_t)n * 64);
+    rec[0] = u32x4{b.x, b.y, b.z, b.w};
+    rec[1] = u32x4{b.x, b.y, b.z, b.w};
+    rec[2] = u32x4{beta[0], beta[1], beta[2], beta[3]};
+    rec[3] = u32x4{beta[4], beta[5], beta[6], beta[7]};
 }
 
 // Exact nearest neighbour of every seed of A among all coarsest pixels of B
@@ -833,16 +861,6 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
 }
 
 // ------------------------------------------------------- line phases ----
-// Blocks are dispatched to the 8 XCDs round-robin by linear block id; the
-// remap gives each XCD a contiguous range of logical blocks, so the lines of
-// one pair and direction (which gather from the same descriptor plane) run
-// on one XCD and share its L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
-}
 
 // One phase of one iteration, one wave per line.
 //   row phase (COL = false, lines = rows, row-major buffers):
@@ -1359,11 +1377,15 @@ __device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, 
 // grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
-    const PairDev& P = pairs[blockIdx.y >> 1];
-    const int dir = blockIdx.y & 1;
+    // neighbouring blocks on one XCD: the gathers at q = p + F(p) then
+    // find the other field's rows in the L2 that fetched them
+    const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int bx = lb % gridDim.x, by = lb / gridDim.x;
+    const PairDev& P = pairs[by >> 1];
+    const int dir = by & 1;
     const LevelDev& L = P.lv[0];
     const int W = L.W, n = L.W * L.H;
-    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    const int i0 = (bx * 256 + threadIdx.x) * 4;
     if (i0 >= n) return;
     const gi2* __restrict__ own = (const gi2*)L.state[dir];
     const gi2* __restrict__ other = (const gi2*)L.state[dir ^ 1];
@@ -1438,11 +1460,15 @@ __global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ 
 // when aligned, as k_fb.  grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
-    const PairDev& P = pairs[blockIdx.y >> 1];
-    const int dir = blockIdx.y & 1;
+    // neighbouring blocks on one XCD: the gathers at q = p + F(p) then
+    // find the other field's rows in the L2 that fetched them
+    const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int bx = lb % gridDim.x, by = lb / gridDim.x;
+    const PairDev& P = pairs[by >> 1];
+    const int dir = by & 1;
     const LevelDev& L = P.lv[0];
     const int W = L.W, n = L.W * L.H;
-    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    const int i0 = (bx * 256 + threadIdx.x) * 4;
     if (i0 >= n) return;
     const gi2* __restrict__ own = (const gi2*)P.save[dir];
     const gi2* __restrict__ inv1 = (const gi2*)P.save[dir ^ 1];
@@ -1494,7 +1520,7 @@ __global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pair
 {
     const PairDev& P = pairs[blockIdx.z >> 1];
     const int dir = blockIdx.z & 1;
-    uint8_t* keep = P.sparse[dir];
+    FF_GLOBAL uint8_t* keep = (FF_GLOBAL uint8_t*)P.sparse[dir];
     if (!keep) return;                                           // output not requested
     const LevelDev& L = P.lv[0];
     const int W = L.W, H = L.H;
@@ -1525,7 +1551,7 @@ __global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pair
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
             const int x = x0 + dx, y = y0 + dy;
-            if (x < W && y < H) keep[(size_t)y * W + x] = (3 * dy + dx == best) ? 1 : 0;
+            if (x < W && y < H) keep[(uint32_t)y * (uint32_t)W + (uint32_t)x] = (3 * dy + dx == best) ? 1 : 0;
         }
     }
 }
