@@ -1370,58 +1370,61 @@ __device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, 
     return ex * ex + ey * ey;
 }
 
-// Four consecutive pixels per thread: 32 bytes of state in two 16-byte
-// loads, the four flows, costs, errors and mask bytes in one store each when
-// the output buffers are 16- and 4-byte aligned; otherwise pixel by pixel.
-// The error plane is written when the table holds one.
-// grid (pixels / 1024, 2 * pairs).
-__global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2, int shift)
+// The consistency kernels: four pixels per thread, 64 apart, so that a wave
+// covers 256 consecutive pixels and each of its load, gather and store
+// instructions touches 64 consecutive ones (the gathers at q = p + F(p) of
+// neighbouring lanes then share cache lines).  Neighbouring blocks run on
+// one XCD, so those gathers find the other field's rows in the L2 that
+// fetched them.  TWO: the two-check form (own = the first search's field,
+// inverse fields = the first search's and the second search's).  The error
+// plane is written when the table holds one.  grid (pixels / 1024, 2 * pairs).
+template <bool TWO>
+__device__ __forceinline__ void fb_pixels(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
-    // neighbouring blocks on one XCD: the gathers at q = p + F(p) then
-    // find the other field's rows in the L2 that fetched them
     const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
     const int bx = lb % gridDim.x, by = lb / gridDim.x;
     const PairDev& P = pairs[by >> 1];
     const int dir = by & 1;
     const LevelDev& L = P.lv[0];
     const int W = L.W, n = L.W * L.H;
-    const int i0 = (bx * 256 + threadIdx.x) * 4;
+    const int i0 = bx * 1024 + (threadIdx.x >> 6) * 256 + (threadIdx.x & 63);
     if (i0 >= n) return;
-    const gi2* __restrict__ own = (const gi2*)L.state[dir];
-    const gi2* __restrict__ other = (const gi2*)L.state[dir ^ 1];
-    uint32_t* fl = reinterpret_cast<uint32_t*>(P.flow[dir]);
-    int32_t* co = P.cost[dir];
-    uint8_t* mk = P.mask[dir];
-    int32_t* er = P.fberr[dir];
-    int y = i0 / W, x = i0 - y * W;
-    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0 &&
-        ((uintptr_t)er & 15u) == 0) {
-        const u32x4 s01 = *(gcu4*)(own + i0), s23 = *(gcu4*)(own + i0 + 2);
-        const i32x2 s[4] = {i32x2{(int)s01.x, (int)s01.y}, i32x2{(int)s01.z, (int)s01.w},
-                            i32x2{(int)s23.x, (int)s23.y}, i32x2{(int)s23.z, (int)s23.w}};
-        uint32_t m = 0;
-        int32_t e[4];
+    const gi2* __restrict__ own = (const gi2*)(TWO ? P.save[dir] : L.state[dir]);
+    const gi2* __restrict__ inv1 = (const gi2*)(TWO ? P.save[dir ^ 1] : L.state[dir ^ 1]);
+    const gi2* __restrict__ inv2 = (const gi2*)L.state[dir ^ 1];
+    FF_GLOBAL uint32_t* fl = (FF_GLOBAL uint32_t*)P.flow[dir];
+    FF_GLOBAL int32_t* co = (FF_GLOBAL int32_t*)P.cost[dir];
+    FF_GLOBAL uint8_t* mk = (FF_GLOBAL uint8_t*)P.mask[dir];
+    FF_GLOBAL int32_t* er = (FF_GLOBAL int32_t*)P.fberr[dir];
+    i32x2 st[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            e[k] = fb_err(other, W, x, y, s[k], shift);
-            m |= (e[k] <= eps2 ? 1u : 0u) << (8 * k);
-            if (++x == W) { x = 0; ++y; }
-        }
-        if (er) *(FF_GLOBAL u32x4*)(er + i0) = u32x4{(uint32_t)e[0], (uint32_t)e[1], (uint32_t)e[2], (uint32_t)e[3]};
-        if (fl) *(FF_GLOBAL u32x4*)(fl + i0) = u32x4{(uint32_t)s[0].x, (uint32_t)s[1].x, (uint32_t)s[2].x, (uint32_t)s[3].x};
-        if (co) *(FF_GLOBAL u32x4*)(co + i0) = u32x4{(uint32_t)s[0].y, (uint32_t)s[1].y, (uint32_t)s[2].y, (uint32_t)s[3].y};
-        if (mk) *(FF_GLOBAL uint32_t*)(mk + i0) = m;
-        return;
+    for (int k = 0; k < 4; ++k) {
+        const int i = i0 + 64 * k;
+        st[k] = i < n ? own[i] : i32x2{0, kInf};                 // INF: nothing gathered
     }
-    for (int i = i0; i < min(i0 + 4, n); ++i) {
-        const i32x2 st = own[i];
-        const int32_t e = fb_err(other, W, x, y, st, shift);
-        if (fl) fl[i] = (uint32_t)st.x;
-        if (co) co[i] = st.y;
-        if (mk) mk[i] = e <= eps2 ? 1 : 0;
-        if (er) er[i] = e;
-        if (++x == W) { x = 0; ++y; }
+    int32_t e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = i0 + 64 * k;
+        const int y = i / W, x = i - y * W;
+        const int32_t e1 = fb_err(inv1, W, x, y, st[k], shift);
+        e[k] = TWO ? max(e1, fb_err(inv2, W, x, y, st[k], shift)) : e1;
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t i = (uint32_t)(i0 + 64 * k);
+        if ((int)i >= n) continue;
+        if (fl) fl[i] = (uint32_t)st[k].x;
+        if (co) co[i] = st[k].y;
+        if (mk) mk[i] = e[k] <= eps2 ? 1 : 0;
+        if (er) er[i] = e[k];
+    }
+}
+
+// Forward-backward check of one search (Sec. 3.1).
+__global__ __launch_bounds__(256) void k_fb(const PairDev* __restrict__ pairs, int eps2, int shift)
+{
+    fb_pixels<false>(pairs, eps2, shift);
 }
 
 // ---------------------------------------------- sub-pixel refinement ----
@@ -1456,56 +1459,10 @@ __global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ 
 // checked against the first search's inverse field B and the second
 // search's B2; the error is the larger of the two (INF when either match is
 // invalid) and the mask is error <= eps^2.  Flow and cost come from the first
-// search.  Four pixels per thread with 16-byte state loads and vector stores
-// when aligned, as k_fb.  grid (pixels / 1024, 2 * pairs).
+// search.  grid (pixels / 1024, 2 * pairs).
 __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, int eps2, int shift)
 {
-    // neighbouring blocks on one XCD: the gathers at q = p + F(p) then
-    // find the other field's rows in the L2 that fetched them
-    const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int bx = lb % gridDim.x, by = lb / gridDim.x;
-    const PairDev& P = pairs[by >> 1];
-    const int dir = by & 1;
-    const LevelDev& L = P.lv[0];
-    const int W = L.W, n = L.W * L.H;
-    const int i0 = (bx * 256 + threadIdx.x) * 4;
-    if (i0 >= n) return;
-    const gi2* __restrict__ own = (const gi2*)P.save[dir];
-    const gi2* __restrict__ inv1 = (const gi2*)P.save[dir ^ 1];
-    const gi2* __restrict__ inv2 = (const gi2*)L.state[dir ^ 1];
-    uint32_t* fl = reinterpret_cast<uint32_t*>(P.flow[dir]);
-    int32_t* co = P.cost[dir];
-    uint8_t* mk = P.mask[dir];
-    int32_t* er = P.fberr[dir];
-    int y = i0 / W, x = i0 - y * W;
-    if (i0 + 4 <= n && ((uintptr_t)fl & 15u) == 0 && ((uintptr_t)co & 15u) == 0 && ((uintptr_t)mk & 3u) == 0 &&
-        ((uintptr_t)er & 15u) == 0) {
-        const u32x4 s01 = *(gcu4*)(own + i0), s23 = *(gcu4*)(own + i0 + 2);
-        const i32x2 s[4] = {i32x2{(int)s01.x, (int)s01.y}, i32x2{(int)s01.z, (int)s01.w},
-                            i32x2{(int)s23.x, (int)s23.y}, i32x2{(int)s23.z, (int)s23.w}};
-        uint32_t m = 0;
-        int32_t e[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            e[k] = max(fb_err(inv1, W, x, y, s[k], shift), fb_err(inv2, W, x, y, s[k], shift));
-            m |= (e[k] <= eps2 ? 1u : 0u) << (8 * k);
-            if (++x == W) { x = 0; ++y; }
-        }
-        if (er) *(FF_GLOBAL u32x4*)(er + i0) = u32x4{(uint32_t)e[0], (uint32_t)e[1], (uint32_t)e[2], (uint32_t)e[3]};
-        if (fl) *(FF_GLOBAL u32x4*)(fl + i0) = u32x4{(uint32_t)s[0].x, (uint32_t)s[1].x, (uint32_t)s[2].x, (uint32_t)s[3].x};
-        if (co) *(FF_GLOBAL u32x4*)(co + i0) = u32x4{(uint32_t)s[0].y, (uint32_t)s[1].y, (uint32_t)s[2].y, (uint32_t)s[3].y};
-        if (mk) *(FF_GLOBAL uint32_t*)(mk + i0) = m;
-        return;
-    }
-    for (int i = i0; i < min(i0 + 4, n); ++i) {
-        const i32x2 st = own[i];
-        const int32_t e = max(fb_err(inv1, W, x, y, st, shift), fb_err(inv2, W, x, y, st, shift));
-        if (fl) fl[i] = (uint32_t)st.x;
-        if (co) co[i] = st.y;
-        if (mk) mk[i] = e <= eps2 ? 1 : 0;
-        if (er) er[i] = e;
-        if (++x == W) { x = 0; ++y; }
-    }
+    fb_pixels<true>(pairs, eps2, shift);
 }
 
 // ----------------------------------------------------- sparsification --
