@@ -377,6 +377,7 @@ __device__ __forceinline__ uint32_t desc_word(s16x2 lo, s16x2 hi, uint32_t bias)
     return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, qh), __builtin_bit_cast(uint32_t, ql), 0x06040200u) ^ bias;
 }
 
+template <bool STREAM>
 __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs, int level)
 {
     const int3 tb = xcd_block3();
@@ -450,14 +451,24 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
         out[i] = make_uint4(desc_word(al + bl, ah + bh, 0x80808000u), desc_word(al - bl, ah - bh, 0x80808080u),
                             desc_word(dl - el, dh - eh, 0x80808080u), desc_word(dl + el, dh + eh, 0x80808080u));
     }
-    // global (not flat) stores: a flat store also counts against the LDS
-    // wait counter, so every LDS wait and barrier below would wait for it
+    // Row-major copy: whole 1 KB runs per store instruction.  STREAM (level 0:
+    // the largest planes, read only by later kernels): non-temporal stores,
+    // which stream through L2 without displacing other data; the coarser
+    // levels' planes are read right after (seed records, coarse line
+    // phases) and stay cached.  The column-major copy's 256-byte runs share
+    // cache lines with the neighbouring tile's and need L2 to merge them:
+    // ordinary stores.
     const int x = x0 + c;
     FF_GLOBAL u32x4* dst = (FF_GLOBAL u32x4*)L.desc[img];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
         const int y = y0 + 8 * g + i;
-        if (x < W && y < H) dst[(uint32_t)y * (uint32_t)W + (uint32_t)x] = u32x4{out[i].x, out[i].y, out[i].z, out[i].w};
+        if (x < W && y < H) {
+            FF_GLOBAL u32x4* q = dst + ((uint32_t)y * (uint32_t)W + (uint32_t)x);
+            const u32x4 v = u32x4{out[i].x, out[i].y, out[i].z, out[i].w};
+            if constexpr (STREAM) __builtin_nontemporal_store(v, q);
+            else *q = v;
+        }
     }
     FF_GLOBAL u32x4* dstT = (FF_GLOBAL u32x4*)L.descT[img];
     for (int half = 0; half < 2; ++half) {                       // column-major, 16 rows at a time
@@ -1540,8 +1551,9 @@ void launch_down2(const PairDev* d, int npairs, int level, int maxpx, hipStream_
 }
 void launch_desc(const PairDev* d, int npairs, int level, int maxW, int maxH, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_desc, dim3((maxW + kDescTX - 1) / kDescTX, (maxH + kDescTY - 1) / kDescTY, 2 * npairs),
-                       dim3(256), 0, st, d, level);
+    const dim3 grid((maxW + kDescTX - 1) / kDescTX, (maxH + kDescTY - 1) / kDescTY, 2 * npairs);
+    if (level == 0) hipLaunchKernelGGL(k_desc<true>, grid, dim3(256), 0, st, d, level);
+    else hipLaunchKernelGGL(k_desc<false>, grid, dim3(256), 0, st, d, level);
 }
 void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, hipStream_t st)
 {
