@@ -5,7 +5,10 @@
 //   gray[l][i]   uint8  [H_l][W_l]        pyramid level l of image i
 //   desc[l][i]   uint8  [H_l][W_l][16]    descriptors, stored biased (d + 128)
 //                                         so the SAD unit works on unsigned bytes
-//   descT[l][i]  uint8  [W_l][H_l][16]    the same descriptors column-major
+//   descT[l][i]  uint8  [W_l][Hp_l][16]   the same descriptors column-major; each
+//                                         column padded to Hp_l = H_l rounded up to
+//                                         16 entries, so every column starts on a
+//                                         128-byte line (padding never read)
 //   state[l][d]  int2   [H_l][W_l]        search state of direction d:
 //                                         .x = flow (int16 dx | int16 dy << 16),
 //                                         .y = cost (INT32_MAX = invalid)
@@ -23,16 +26,20 @@ namespace ff {
 constexpr int kMaxLevels = 8;
 constexpr int kMaxSide = 8192;
 constexpr int32_t kInf = 0x7FFFFFFF;
+// Column stride of the column-major feature planes: H rounded up to 16
+// entries, so that every column starts on a 128-byte line.
+inline int padded_height(int H) { return (H + 15) & ~15; }
 
 struct LevelDev {
     int W, H;
+    int Hp;                          // column stride of descT / cenT (H rounded up to 16)
     uint8_t* gray[2];
     uint8_t* desc[2];
     uint8_t* descT[2];
     int2* state[2];
     int2* stateT[2];
     uint8_t* cen[2];                 // 7x7 Census strings, u64 per pixel (Census cost only)
-    uint8_t* cenT[2];                // column-major copy
+    uint8_t* cenT[2];                // column-major copy, columns Hp apart
 };
 
 struct PairDev {

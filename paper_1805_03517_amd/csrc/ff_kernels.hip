@@ -98,23 +98,13 @@ __device__ __forceinline__ int3 xcd_block3()
     return make_int3(r % gridDim.x, r / gridDim.x, z);
 }
 
-// Index of pixel (x, y) in a row-major ([H][W]) or column-major ([W][H]) plane.
+// Index of pixel (x, y) in a row-major ([H][W]) feature plane, or in a
+// column-major one whose columns are CS entries apart (CS = the level's Hp:
+// H rounded up so that every column starts on a 128-byte line).
 template <bool COL>
-__device__ __forceinline__ size_t pix(int x, int y, int W, int H)
+__device__ __forceinline__ size_t pix(int x, int y, int W, int CS)
 {
-    return COL ? (size_t)x * H + y : (size_t)y * W + x;
-}
-
-// Matching cost of pixel (x, y) of A under flow f against descriptor plane
-// DB (Sec. 3.1: a distance of feature descriptors).  INF when the target
-// leaves the image; no load is issued then.  COL selects DB's layout.
-template <bool COL = false>
-__device__ __forceinline__ int32_t cost_at(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f, uint4 a)
-{
-    int qx = x + flow_x(f), qy = y + flow_y(f);
-    if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-    const uint4 b = ld16(DB + pix<COL>(qx, qy, W, H) * 16);
-    return sad16(a, b);
+    return COL ? (size_t)x * CS + y : (size_t)y * W + x;
 }
 
 __device__ __forceinline__ uint4 load_desc(gcu8* __restrict__ D, size_t idx)
@@ -172,15 +162,16 @@ __device__ __forceinline__ uint32_t bilerp_word(uint32_t b00, uint32_t b10, uint
 // itself, so no read leaves the image (four loads whatever the fraction:
 // skipping them per lane measured slower).  INF outside.
 template <bool COL>
-__device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f, uint4 a)
+__device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int H, int CS, int x, int y, uint32_t f,
+                                               uint4 a)
 {
     const int tx = 4 * x + flow_x(f), ty = 4 * y + flow_y(f);
     if (tx < 0 || ty < 0) return kInf;
     const int ix = tx >> 2, iy = ty >> 2, ax = tx & 3, ay = ty & 3;
     if (ix > W - 1 || iy > H - 1 || (ix == W - 1 && ax) || (iy == H - 1 && ay)) return kInf;
     const int ix1 = ax ? ix + 1 : ix, iy1 = ay ? iy + 1 : iy;
-    const uint4 b00 = ld16(DB + pix<COL>(ix, iy, W, H) * 16), b10 = ld16(DB + pix<COL>(ix1, iy, W, H) * 16);
-    const uint4 b01 = ld16(DB + pix<COL>(ix, iy1, W, H) * 16), b11 = ld16(DB + pix<COL>(ix1, iy1, W, H) * 16);
+    const uint4 b00 = ld16(DB + pix<COL>(ix, iy, W, CS) * 16), b10 = ld16(DB + pix<COL>(ix1, iy, W, CS) * 16);
+    const uint4 b01 = ld16(DB + pix<COL>(ix, iy1, W, CS) * 16), b11 = ld16(DB + pix<COL>(ix1, iy1, W, CS) * 16);
     const uint32_t w00 = (4 - ax) * (4 - ay), w10 = ax * (4 - ay), w01 = (4 - ax) * ay, w11 = ax * ay;
     const uint4 i = make_uint4(bilerp_word(b00.x, b10.x, b01.x, b11.x, w00, w10, w01, w11),
                                bilerp_word(b00.y, b10.y, b01.y, b11.y, w00, w10, w01, w11),
@@ -190,18 +181,18 @@ __device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int
 }
 
 // Matching cost of pixel (x, y) of A, feature a, under flow f against the
-// feature plane DB of B (layout by COL); INF when the target leaves the
-// image, and then no load is issued.
+// feature plane DB of B (layout by COL, column stride CS); INF when the
+// target leaves the image, and then no load is issued.
 template <bool COL, int CK>
-__device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H, int x, int y, uint32_t f,
+__device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H, int CS, int x, int y, uint32_t f,
                                              typename Feat<CK>::T a)
 {
     if constexpr (CK == 2) {
-        return subpix_cost<COL>(DB, W, H, x, y, f, a);
+        return subpix_cost<COL>(DB, W, H, CS, x, y, f, a);
     } else {
         const int qx = x + flow_x(f), qy = y + flow_y(f);
         if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-        return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)));
+        return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, CS)));
     }
 }
 
@@ -485,7 +476,7 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
             const int xx = x0 + cc, yy = y0 + 16 * half + r;
             if (xx < W && yy < H) {
                 const uint4 w = sm.res[r][cc];
-                dstT[(uint32_t)xx * (uint32_t)H + (uint32_t)yy] = u32x4{w.x, w.y, w.z, w.w};
+                dstT[(uint32_t)xx * (uint32_t)L.Hp + (uint32_t)yy] = u32x4{w.x, w.y, w.z, w.w};
             }
         }
     }
@@ -582,7 +573,7 @@ __global__ __launch_bounds__(256) void k_census(const PairDev* __restrict__ pair
             const int xx = x0 + cc, yy = y0 + 16 * half + r;
             if (xx < W && yy < H) {
                 const uint2 w = sm.res[r][cc];
-                dstT[(uint32_t)xx * (uint32_t)H + (uint32_t)yy] = u32x2{w.x, w.y};
+                dstT[(uint32_t)xx * (uint32_t)L.Hp + (uint32_t)yy] = u32x2{w.x, w.y};
             }
         }
     }
@@ -866,8 +857,8 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
     if (i >= W * H) return;
     const int x = i % W, y = i / W;
     const uint32_t f = init_flow(P, dir, level, coarsest != 0, stride, W, x, y);
-    const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
-                             : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
+    const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, W, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
+                             : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, W, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
     L.state[dir][i] = make_int2((int)f, c);
 }
 
@@ -914,7 +905,8 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
 template <int RC, bool COL, int CH, int CK>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
-                                                    bool lin, bool lout, LdsLine lline, int W, int H, int len, int line,
+                                                    bool lin, bool lout, LdsLine lline, int W, int H, int CS, int len,
+                                                    int line,
                                                     int lane,
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
                                                     const SearchConst& sc, const PairDev& P, int dir, int initc)
@@ -938,7 +930,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
             if (valid) {
                 if (initc) {                                     // row phase, first pass of iteration 0
                     const uint32_t f = init_flow(P, dir, (int)level, initc == 2, sc.stride, W, p, line);
-                    st = i32x2{(int)f, feat_cost<false, CK>(DB, W, H, p, line, f, A[c])};
+                    st = i32x2{(int)f, feat_cost<false, CK>(DB, W, H, CS, p, line, f, A[c])};
                 } else {
                     st = (lin && lline.has(p)) ? lline.get(p) : Sin[(uint32_t)p * (uint32_t)sstr];
                 }
@@ -1013,7 +1005,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                         const int p = w0 + 64 * c + lane;
                         lp[c] = pred[c];
                         le[c] = pred[c] == f0[c] ? c0[c]
-                                                 : feat_cost<COL, CK>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
+                                                 : feat_cost<COL, CK>(DB, W, H, CS, COL ? line : p, COL ? p : line, pred[c], a[c]);
                     }
                 }
             }
@@ -1055,7 +1047,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     // running best's upper bound: never selected, not gathered
                     const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H && (qdx | qdy) != 0;
                     pin[c] |= in ? (1u << j) : 0u;
-                    pdesc[c][j] = in ? Feat<CK>::load(DB, pix<COL>(qx, qy, W, H)) : Feat<CK>::zero();
+                    pdesc[c][j] = in ? Feat<CK>::load(DB, pix<COL>(qx, qy, W, CS)) : Feat<CK>::zero();
                 }
             }
             pend = true;
@@ -1122,8 +1114,9 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
+    const int CS = COL ? L.Hp : W;                               // feature-plane line stride
     gcu8* __restrict__ DA = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
-                            (size_t)line * len * FB;
+                            (size_t)line * CS * FB;
     gcu8* __restrict__ DB = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
                                             : (COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]));
     gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
@@ -1176,7 +1169,8 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
 
         if constexpr (!STG && RC > 0 && CH <= 2 && CK != 2) {      // the sub-pixel refinement: generic pass
             if (active)
-                line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, len, line, lane, fwd, rs,
+                line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, CS, len, line, lane, fwd,
+                                                     rs,
                                                  (uint32_t)level, ctr2, sc, P, dir,
                                                  (!COL && fwd && finit) ? (level == sc.levels - 1 ? 2 : 1) : 0);
             continue;
@@ -1250,7 +1244,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                         const int ri = 64 * k + lane, gi = si0 + ri;
                         if (ri < RI && gi >= 0 && gi < len)
                             __builtin_amdgcn_global_load_lds(
-                                (const FF_GLOBAL void*)(DB + ((size_t)gj * len + gi) * 16),
+                                (const FF_GLOBAL void*)(DB + ((size_t)gj * CS + gi) * 16),
                                 (__attribute__((address_space(3))) void*)&region[rj * RI + 64 * k], 16, 0, 0);
                     }
                 }
@@ -1280,7 +1274,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                         const int p = w0 + 64 * c + lane;
                         lp[c] = pred[c];
                         le[c] = pred[c] == f0[c] ? c0[c]
-                                                 : feat_cost<COL, CK>(DB, W, H, COL ? line : p, COL ? p : line, pred[c], a[c]);
+                                                 : feat_cost<COL, CK>(DB, W, H, CS, COL ? line : p, COL ? p : line, pred[c], a[c]);
                     }
                 }
 #pragma unroll
@@ -1310,11 +1304,11 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                             const int ri = (COL ? qy : qx) - si0, rj = (COL ? qx : qy) - sj0;
                             if ((unsigned)ri < (unsigned)RI && (unsigned)rj < (unsigned)RJ)
                                 return sad16(ac, region[rj * RI + ri]);
-                            return sad16(ac, ld16(DB + pix<COL>(qx, qy, W, H) * 16));
+                            return sad16(ac, ld16(DB + pix<COL>(qx, qy, W, CS) * 16));
                         });
                     } else {
                         random_search<RC>(bf, bc, W, x, y, rlev, ctr2, sc,
-                                          [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, x, y, f, ac); });
+                                          [&](uint32_t f) { return feat_cost<COL, CK>(DB, W, H, CS, x, y, f, ac); });
                     }
                 }
                 if (lout && lline.has(p)) lline.set(p, i32x2{(int)bf, bc});

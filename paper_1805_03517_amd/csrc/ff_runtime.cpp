@@ -160,11 +160,11 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
     for (int l = 0; l < p.levels; ++l) {
         pl.W[l] = l == 0 ? W : pl.W[l - 1] >> 1;
         pl.H[l] = l == 0 ? H : pl.H[l - 1] >> 1;
-        const size_t n = (size_t)pl.W[l] * pl.H[l];
+        const size_t n = (size_t)pl.W[l] * pl.H[l], nT = (size_t)pl.W[l] * padded_height(pl.H[l]);
         b += 2 * align_up(n);            // gray planes
-        b += 4 * align_up(n * 16);       // descriptors, row- and column-major
+        b += 2 * align_up(n * 16) + 2 * align_up(nT * 16);   // descriptors, row- and column-major
         b += 4 * align_up(n * 8);        // state, row- and column-major
-        if (p.flags & FF_COST_CENSUS) b += 4 * align_up(n * 8);   // Census strings, both layouts
+        if (p.flags & FF_COST_CENSUS) b += 2 * align_up(n * 8) + 2 * align_up(nT * 8);   // Census strings
     }
     const int c = p.levels - 1;
     pl.nsx = (pl.W[c] + p.seed_stride - 1) / p.seed_stride;
@@ -278,14 +278,16 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
             LevelDev& L = d.lv[l];
             L.W = pl.W[l];
             L.H = pl.H[l];
+            L.Hp = padded_height(pl.H[l]);
+            const size_t npT = (size_t)L.W * L.Hp;
             for (int k = 0; k < 2; ++k) L.gray[k] = (uint8_t*)take(np);
             for (int k = 0; k < 2; ++k) L.desc[k] = (uint8_t*)take(np * 16);
-            for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(np * 16);
+            for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(npT * 16);
             for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take(np * 8);
             for (int k = 0; k < 2; ++k) L.stateT[k] = (int2*)take(np * 8);
             if (p.flags & FF_COST_CENSUS) {
                 for (int k = 0; k < 2; ++k) L.cen[k] = (uint8_t*)take(np * 8);
-                for (int k = 0; k < 2; ++k) L.cenT[k] = (uint8_t*)take(np * 8);
+                for (int k = 0; k < 2; ++k) L.cenT[k] = (uint8_t*)take(npT * 8);
             }
         }
         const int c = p.levels - 1;
