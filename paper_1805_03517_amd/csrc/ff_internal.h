@@ -9,7 +9,9 @@
 //                                         column padded to Hp_l = H_l rounded up to
 //                                         16 entries, so every column starts on a
 //                                         128-byte line (padding never read)
-//   state[l][d]  int2   [H_l][W_l]        search state of direction d:
+//   state[l][d]  int2   [H_l][Wp_l]       search state of direction d, rows padded
+//                                         to Wp_l = W_l rounded up to 16 entries
+//                                         (every row starts on a 128-byte line):
 //                                         .x = flow (int16 dx | int16 dy << 16),
 //                                         .y = cost (INT32_MAX = invalid)
 //   stateT[l][d] int2   [W_l][H_l]        column-major copy used by the column phase
@@ -29,10 +31,14 @@ constexpr int32_t kInf = 0x7FFFFFFF;
 // Column stride of the column-major feature planes: H rounded up to 16
 // entries, so that every column starts on a 128-byte line.
 inline int padded_height(int H) { return (H + 15) & ~15; }
+// Row stride of the row-major state planes (8-byte entries): W rounded up to
+// 16, so that every row starts on a 128-byte line.
+inline int padded_width(int W) { return (W + 15) & ~15; }
 
 struct LevelDev {
     int W, H;
     int Hp;                          // column stride of descT / cenT (H rounded up to 16)
+    int Wp;                          // row stride of state (W rounded up to 16)
     uint8_t* gray[2];
     uint8_t* desc[2];
     uint8_t* descT[2];

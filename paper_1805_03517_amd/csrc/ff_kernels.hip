@@ -842,7 +842,7 @@ __device__ __forceinline__ uint32_t init_flow(const PairDev& P, int dir, int lev
     }
     const LevelDev& C = P.lv[level + 1];
     const int cx = min(x >> 1, C.W - 1), cy = min(y >> 1, C.H - 1);
-    const uint32_t cf = (uint32_t)((const gi2*)C.state[dir])[(uint32_t)cy * (uint32_t)C.W + (uint32_t)cx].x;
+    const uint32_t cf = (uint32_t)((const gi2*)C.state[dir])[(uint32_t)cy * (uint32_t)C.Wp + (uint32_t)cx].x;
     return pack_flow(2 * flow_x(cf), 2 * flow_y(cf));
 }
 
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
     const uint32_t f = init_flow(P, dir, level, coarsest != 0, stride, W, x, y);
     const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, W, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
                              : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, W, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
-    L.state[dir][i] = make_int2((int)f, c);
+    L.state[dir][(size_t)y * L.Wp + x] = make_int2((int)f, c);
 }
 
 // ------------------------------------------------------- line phases ----
@@ -1119,7 +1119,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                             (size_t)line * CS * FB;
     gcu8* __restrict__ DB = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
                                             : (COL ? L.descT[dir ^ 1] : L.desc[dir ^ 1]));
-    gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * len;
+    gi2* __restrict__ S = (gi2*)(COL ? L.stateT[dir] : L.state[dir]) + (size_t)line * (COL ? len : L.Wp);
     constexpr int WIN = 64 * CH;
     const int nwin = (len + WIN - 1) / WIN;
 
@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const int nl = min(WPB, nlines - line0);
         for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
             const int k = e % WPB, p = e / WPB;
-            if (k < nl) line_lds(k).set(p, src[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)]);
+            if (k < nl) line_lds(k).set(p, src[(uint32_t)p * (uint32_t)L.Wp + (uint32_t)(line0 + k)]);
         }
         __syncthreads();
     }
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const uint32_t ctr2 = ((uint32_t)iter << 2) | rs_pass;
         // the column phase's first pass reads the row-major state in place
         const gi2* __restrict__ Sin = (COL && fwd) ? (const gi2*)L.state[dir] + line : S;
-        const int sstr = (COL && fwd) ? W : 1;
+        const int sstr = (COL && fwd) ? L.Wp : 1;
         const bool lin = xwk && (COL || !fwd);
         const bool lout = xwk && (COL || (fwd && upto >= 2));
         const bool quarter = CK == 2 && !COL && fwd && finit;
@@ -1323,7 +1323,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const int nl = min(WPB, nlines - line0);
         for (int e = threadIdx.x; e < WPB * len; e += 64 * WPB) {
             const int k = e % WPB, p = e / WPB;
-            if (k < nl) dst[(uint32_t)p * (uint32_t)W + (uint32_t)(line0 + k)] = line_lds(k).get(p);
+            if (k < nl) dst[(uint32_t)p * (uint32_t)L.Wp + (uint32_t)(line0 + k)] = line_lds(k).get(p);
         }
     }
 }
@@ -1338,6 +1338,7 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
     const int dir = blockIdx.z & 1;
     const LevelDev& L = P.lv[level];
     const int SW = to_t ? L.W : L.H, SH = to_t ? L.H : L.W;     // source is [SH][SW]
+    const int sp = to_t ? L.Wp : L.H, dp = to_t ? L.H : L.Wp;   // source / destination row strides
     const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
     if (x0 >= SW || y0 >= SH) return;
     const int2* __restrict__ src = to_t ? L.state[dir] : L.stateT[dir];
@@ -1346,12 +1347,12 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int y = y0 + r, x = x0 + tx;
-        if (y < SH && x < SW) t[r][tx] = src[(size_t)y * SW + x];
+        if (y < SH && x < SW) t[r][tx] = src[(size_t)y * sp + x];
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int xx = x0 + r, yy = y0 + tx;                     // destination is [SW][SH]
-        if (xx < SW && yy < SH) dst[(size_t)xx * SH + yy] = t[tx][r];
+        if (xx < SW && yy < SH) dst[(size_t)xx * dp + yy] = t[tx][r];
     }
 }
 
@@ -1363,13 +1364,13 @@ __global__ __launch_bounds__(256) void k_transpose_state(const PairDev* __restri
 // invalid (a finite cost means q lies inside the image).  mask = err <= eps^2.
 // Flows in 1 / 2^shift pixels (shift 2 after the sub-pixel refinement): q is
 // then rounded half up to whole pixels and the error is in 1 / 4^shift px^2.
-__device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int W, int x, int y, i32x2 s, int shift)
+__device__ __forceinline__ int32_t fb_err(const gi2* __restrict__ other, int Wp, int x, int y, i32x2 s, int shift)
 {
     if (s.y == kInf) return kInf;
     const uint32_t F = (uint32_t)s.x;
     const int half = shift ? 1 << (shift - 1) : 0;
     const int qx = x + ((flow_x(F) + half) >> shift), qy = y + ((flow_y(F) + half) >> shift);
-    const i32x2 t = other[(uint32_t)qy * (uint32_t)W + (uint32_t)qx];
+    const i32x2 t = other[(uint32_t)qy * (uint32_t)Wp + (uint32_t)qx];
     if (t.y == kInf) return kInf;
     const int ex = flow_x(F) + flow_x((uint32_t)t.x), ey = flow_y(F) + flow_y((uint32_t)t.x);
     return ex * ex + ey * ey;
@@ -1401,19 +1402,21 @@ __device__ __forceinline__ void fb_pixels(const PairDev* __restrict__ pairs, int
     FF_GLOBAL int32_t* co = (FF_GLOBAL int32_t*)P.cost[dir];
     FF_GLOBAL uint8_t* mk = (FF_GLOBAL uint8_t*)P.mask[dir];
     FF_GLOBAL int32_t* er = (FF_GLOBAL int32_t*)P.fberr[dir];
+    const int Wp = L.Wp;                                         // state rows are Wp apart
     i32x2 st[4];
+    int px[4], py[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = i0 + 64 * k;
-        st[k] = i < n ? own[i] : i32x2{0, kInf};                 // INF: nothing gathered
+        py[k] = i / W;
+        px[k] = i - py[k] * W;
+        st[k] = i < n ? own[(uint32_t)py[k] * (uint32_t)Wp + (uint32_t)px[k]] : i32x2{0, kInf};   // INF: nothing gathered
     }
     int32_t e[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int i = i0 + 64 * k;
-        const int y = i / W, x = i - y * W;
-        const int32_t e1 = fb_err(inv1, W, x, y, st[k], shift);
-        e[k] = TWO ? max(e1, fb_err(inv2, W, x, y, st[k], shift)) : e1;
+        const int32_t e1 = fb_err(inv1, Wp, px[k], py[k], st[k], shift);
+        e[k] = TWO ? max(e1, fb_err(inv2, Wp, px[k], py[k], st[k], shift)) : e1;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1442,7 +1445,8 @@ __global__ __launch_bounds__(256) void k_to_quarter(const PairDev* __restrict__ 
     const LevelDev& L = P.lv[0];
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= L.W * L.H) return;
-    gi2* s = (gi2*)L.state[dir] + i;
+    const int y = i / L.W, x = i - y * L.W;
+    gi2* s = (gi2*)L.state[dir] + ((size_t)y * L.Wp + x);
     const uint32_t f = (uint32_t)(*s).x;
     (*s).x = (int)pack_flow(4 * flow_x(f), 4 * flow_y(f));
 }
@@ -1457,7 +1461,8 @@ __global__ __launch_bounds__(256) void k_save_state(const PairDev* __restrict__ 
     const LevelDev& L = P.lv[0];
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= L.W * L.H) return;
-    ((gi2*)P.save[dir])[i] = ((const gi2*)L.state[dir])[i];
+    const size_t j = (size_t)(i / L.W) * L.Wp + (size_t)(i % L.W);  // both planes rows Wp apart
+    ((gi2*)P.save[dir])[j] = ((const gi2*)L.state[dir])[j];
 }
 
 // Two consistency checks (Sec. 3.1): p of the first search's field F is

@@ -163,7 +163,7 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
         const size_t n = (size_t)pl.W[l] * pl.H[l], nT = (size_t)pl.W[l] * padded_height(pl.H[l]);
         b += 2 * align_up(n);            // gray planes
         b += 2 * align_up(n * 16) + 2 * align_up(nT * 16);   // descriptors, row- and column-major
-        b += 4 * align_up(n * 8);        // state, row- and column-major
+        b += 2 * align_up((size_t)padded_width(pl.W[l]) * pl.H[l] * 8) + 2 * align_up(n * 8);   // state, both layouts
         if (p.flags & FF_COST_CENSUS) b += 2 * align_up(n * 8) + 2 * align_up(nT * 8);   // Census strings
     }
     const int c = p.levels - 1;
@@ -172,7 +172,7 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
     b += 2 * align_up((size_t)pl.W[c] * pl.H[c] * 64);
     b += 2 * align_up((size_t)pl.nsx * pl.nsy * 8);
     if (p.flags & FF_SPARSIFY) b += 2 * align_up((size_t)W * H * 4);   // consistency errors
-    if (p.flags & FF_SECOND_CHECK) b += 2 * align_up((size_t)W * H * 8);   // first search's level-0 state
+    if (p.flags & FF_SECOND_CHECK) b += 2 * align_up((size_t)padded_width(W) * H * 8);   // first search's level-0 state
     pl.bytes = b;
     return pl;
 }
@@ -279,11 +279,12 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
             L.W = pl.W[l];
             L.H = pl.H[l];
             L.Hp = padded_height(pl.H[l]);
+            L.Wp = padded_width(pl.W[l]);
             const size_t npT = (size_t)L.W * L.Hp;
             for (int k = 0; k < 2; ++k) L.gray[k] = (uint8_t*)take(np);
             for (int k = 0; k < 2; ++k) L.desc[k] = (uint8_t*)take(np * 16);
             for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(npT * 16);
-            for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take(np * 8);
+            for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take((size_t)L.Wp * L.H * 8);
             for (int k = 0; k < 2; ++k) L.stateT[k] = (int2*)take(np * 8);
             if (p.flags & FF_COST_CENSUS) {
                 for (int k = 0; k < 2; ++k) L.cen[k] = (uint8_t*)take(np * 8);
@@ -304,7 +305,7 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
         d.sparse[0] = pairs[i].sparse_fwd;
         d.sparse[1] = pairs[i].sparse_bwd;
         if (p.flags & FF_SECOND_CHECK)
-            for (int k = 0; k < 2; ++k) d.save[k] = (int2*)take((size_t)pl.W[0] * pl.H[0] * 8);
+            for (int k = 0; k < 2; ++k) d.save[k] = (int2*)take((size_t)padded_width(pl.W[0]) * pl.H[0] * 8);
         if (p.flags & FF_SPARSIFY) {
             const size_t np = (size_t)pl.W[0] * pl.H[0];
             for (int k = 0; k < 2; ++k) {
@@ -422,6 +423,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     const int L = p.levels, c = L - 1;
     const SearchConst sc = search_const(p);
     auto level_px = [&](int l) { return (size_t)plan0->W[l] * plan0->H[l]; };
+    // a level's state for a debug stop: rows Wp apart on the device, packed [H][W] for the caller
+    auto copy_state = [&](int l) {
+        const LevelDev& V = tab0->lv[l];
+        return hipMemcpy2DAsync(stop.dst, (size_t)V.W * 8, V.state[stop.st.dir], (size_t)V.Wp * 8, (size_t)V.W * 8,
+                                (size_t)V.H, hipMemcpyDeviceToDevice, st);
+    };
 
     FF_TRACED(KN_GRAY, 0, launch_gray(d, n, D.maxPx[0], st));
     if (stop.active && stop.st.kind == FF_STAGE_GRAY) {
@@ -478,7 +485,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             if (!fuse)
                 FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
             if (stop_here && stop.st.step == 0) {
-                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
+                FF_HIP(h, copy_state(l));
                 return FF_OK;
             }
             for (int t = 0; t < p.iters; ++t) {
@@ -495,8 +502,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                         FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
                 }
                 if (last) {
-                    FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].state[stop.st.dir], level_px(l) * 8,
-                                             hipMemcpyDeviceToDevice, st));
+                    FF_HIP(h, copy_state(l));
                     return FF_OK;
                 }
             }
@@ -509,7 +515,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
             const bool stop_sub = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == L;
             if (stop_sub && stop.st.step == 0) {
                 FF_TRACED(KN_QUARTER, 0, launch_to_quarter(d, n, D.maxPx[0], st));
-                FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].state[stop.st.dir], level_px(0) * 8, hipMemcpyDeviceToDevice, st));
+                FF_HIP(h, copy_state(0));
                 return FF_OK;
             }
             // fixed schedule, (1, 8) rows and (1, 4) columns: the fastest of
@@ -531,8 +537,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                         FF_TRACED(KN_TRANS, 0, launch_transpose_state(d, n, 0, 0, D.maxW[0], D.maxH[0], st));
                 }
                 if (last) {
-                    FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[0].state[stop.st.dir], level_px(0) * 8,
-                                             hipMemcpyDeviceToDevice, st));
+                    FF_HIP(h, copy_state(0));
                     return FF_OK;
                 }
             }
