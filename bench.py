@@ -36,7 +36,7 @@ SCHEDULE_C1 = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0, 1,
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "20a0830dc1f8d156", "bytes_per_launch": 1858997573}
+TRAFFIC = {"kernel_sha": "bf293402885ebd3d", "bytes_per_launch": 1781790844}
 
 
 def kernel_sha():
