@@ -3,7 +3,8 @@
 //
 // HBM layout per pair (all buffers 256-byte aligned, carved from one arena):
 //   gray[l][i]   uint8  [H_l][W_l]        pyramid level l of image i
-//   desc[l][i]   uint8  [H_l][W_l][16]    descriptors, stored biased (d + 128)
+//   desc[l][i]   uint8  [H_l][Wp_l][16]   descriptors, stored biased (d + 128),
+//                                         rows padded to Wp_l entries
 //                                         so the SAD unit works on unsigned bytes
 //   descT[l][i]  uint8  [W_l][Hp_l][16]   the same descriptors column-major; each
 //                                         column padded to Hp_l = H_l rounded up to
@@ -11,7 +12,9 @@
 //                                         128-byte line (padding never read)
 //   state[l][d]  int2   [H_l][Wp_l]       search state of direction d, rows padded
 //                                         to Wp_l = W_l rounded up to 16 entries
-//                                         (every row starts on a 128-byte line):
+//                                         (every row of every row-major plane then
+//                                         starts on a 128-byte line; padding never
+//                                         read):
 //                                         .x = flow (int16 dx | int16 dy << 16),
 //                                         .y = cost (INT32_MAX = invalid)
 //   stateT[l][d] int2   [W_l][H_l]        column-major copy used by the column phase
@@ -31,20 +34,20 @@ constexpr int32_t kInf = 0x7FFFFFFF;
 // Column stride of the column-major feature planes: H rounded up to 16
 // entries, so that every column starts on a 128-byte line.
 inline int padded_height(int H) { return (H + 15) & ~15; }
-// Row stride of the row-major state planes (8-byte entries): W rounded up to
-// 16, so that every row starts on a 128-byte line.
+// Row stride of the row-major state, descriptor and Census planes: W rounded
+// up to 16, so that every row starts on a 128-byte line.
 inline int padded_width(int W) { return (W + 15) & ~15; }
 
 struct LevelDev {
     int W, H;
     int Hp;                          // column stride of descT / cenT (H rounded up to 16)
-    int Wp;                          // row stride of state (W rounded up to 16)
+    int Wp;                          // row stride of state, desc and cen (W rounded up to 16)
     uint8_t* gray[2];
     uint8_t* desc[2];
     uint8_t* descT[2];
     int2* state[2];
     int2* stateT[2];
-    uint8_t* cen[2];                 // 7x7 Census strings, u64 per pixel (Census cost only)
+    uint8_t* cen[2];                 // 7x7 Census strings, u64 per pixel, rows Wp apart (Census cost only)
     uint8_t* cenT[2];                // column-major copy, columns Hp apart
 };
 

@@ -98,13 +98,15 @@ __device__ __forceinline__ int3 xcd_block3()
     return make_int3(r % gridDim.x, r / gridDim.x, z);
 }
 
-// Index of pixel (x, y) in a row-major ([H][W]) feature plane, or in a
-// column-major one whose columns are CS entries apart (CS = the level's Hp:
-// H rounded up so that every column starts on a 128-byte line).
+// Index of pixel (x, y) in a row-major feature plane whose rows are CS
+// entries apart (CS = the level's Wp), or in a column-major one whose
+// columns are CS entries apart (CS = the level's Hp): W or H rounded up so
+// that every line of the plane starts on a 128-byte line.
 template <bool COL>
 __device__ __forceinline__ size_t pix(int x, int y, int W, int CS)
 {
-    return COL ? (size_t)x * CS + y : (size_t)y * W + x;
+    (void)W;
+    return COL ? (size_t)x * CS + y : (size_t)y * CS + x;
 }
 
 __device__ __forceinline__ uint4 load_desc(gcu8* __restrict__ D, size_t idx)
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(256) void k_desc(const PairDev* __restrict__ pairs,
     for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
         const int y = y0 + 8 * g + i;
         if (x < W && y < H) {
-            FF_GLOBAL u32x4* q = dst + ((uint32_t)y * (uint32_t)W + (uint32_t)x);
+            FF_GLOBAL u32x4* q = dst + ((uint32_t)y * (uint32_t)L.Wp + (uint32_t)x);
             const u32x4 v = u32x4{out[i].x, out[i].y, out[i].z, out[i].w};
             if constexpr (STREAM) __builtin_nontemporal_store(v, q);
             else *q = v;
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(256) void k_census(const PairDev* __restrict__ pair
 #pragma unroll
     for (int i = 0; i < 8; ++i) {                                // row-major: lanes along x
         const int y = y0 + 8 * g + i;
-        if (x < W && y < H) dst[(uint32_t)y * (uint32_t)W + (uint32_t)x] = u32x2{out[i].x, out[i].y};
+        if (x < W && y < H) dst[(uint32_t)y * (uint32_t)L.Wp + (uint32_t)x] = u32x2{out[i].x, out[i].y};
     }
     FF_GLOBAL u32x2* dstT = (FF_GLOBAL u32x2*)L.cenT[img];
     for (int half = 0; half < 2; ++half) {                       // column-major, 16 rows at a time
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n < P.nsx * P.nsy) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
     if (n >= N) return;
-    const uint4 db = load_desc((gcu8*)L.desc[img], n);
+    const uint4 db = load_desc((gcu8*)L.desc[img], (size_t)(n / L.W) * L.Wp + (size_t)(n % L.W));
     const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
     const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
     int nb = 0;
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
             A[mq] = v4i{0x7F7F7F7F, 0x7F7F7F7F, 0x7F7F7F7F, g == 2 ? 0x7F7F7F7F : 0x017F7F7F};
         } else if (q < Q) {
             const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
-            const uint4 d = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
+            const uint4 d = load_desc((gcu8*)L.desc[dir], (size_t)sy * L.Wp + sx);
             A[mq] = v4i{(int)(d.x ^ 0x80808080u), (int)(d.y ^ 0x80808080u), (int)(d.z ^ 0x80808080u),
                         (int)(d.w ^ 0x80808080u)};
         } else {
@@ -787,7 +789,7 @@ __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict_
     int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     if (live) {
         const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
-        const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * W + sx);
+        const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * L.Wp + sx);
         a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
         a3 = (int)(ad.w ^ 0x80808080u);
     }
@@ -800,7 +802,8 @@ __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict_
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
-            bd[k] = n < (uint32_t)N ? load_desc(DBd, n) : make_uint4(0, 0, 0, 0);
+            bd[k] = n < (uint32_t)N ? load_desc(DBd, (size_t)(n / (uint32_t)W) * L.Wp + (n % (uint32_t)W))
+                                    : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -857,8 +860,10 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
     if (i >= W * H) return;
     const int x = i % W, y = i / W;
     const uint32_t f = init_flow(P, dir, level, coarsest != 0, stride, W, x, y);
-    const int32_t c = census ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, W, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], i))
-                             : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, W, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], i));
+    const size_t ip = (size_t)y * L.Wp + x;                     // row-major planes: rows Wp apart
+    const int32_t c = census
+                          ? feat_cost<false, 1>((gcu8*)L.cen[dir ^ 1], W, H, L.Wp, x, y, f, Feat<1>::load((gcu8*)L.cen[dir], ip))
+                          : feat_cost<false, 0>((gcu8*)L.desc[dir ^ 1], W, H, L.Wp, x, y, f, Feat<0>::load((gcu8*)L.desc[dir], ip));
     L.state[dir][(size_t)y * L.Wp + x] = make_int2((int)f, c);
 }
 
@@ -1114,7 +1119,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
     if (!STG && !active && !xwc) return;
-    const int CS = COL ? L.Hp : W;                               // feature-plane line stride
+    const int CS = COL ? L.Hp : L.Wp;                            // feature-plane line stride
     gcu8* __restrict__ DA = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
                             (size_t)line * CS * FB;
     gcu8* __restrict__ DB = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir ^ 1] : L.cen[dir ^ 1])
@@ -1524,10 +1529,14 @@ __global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pair
 }
 
 // ------------------------------------------------------------- debug ----
-__global__ void k_copy_desc_signed(const uint8_t* __restrict__ src, int8_t* __restrict__ dst, size_t n)
+// Descriptors of one level as signed bytes, packed [H][W][16] (the plane's
+// rows are Wp entries apart).
+__global__ void k_copy_desc_signed(const uint8_t* __restrict__ src, int8_t* __restrict__ dst, int W, int H, int Wp)
 {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) dst[i] = (int8_t)(src[i] ^ 0x80u);
+    if (i >= (size_t)W * H * 16) return;
+    const size_t px = i >> 4, y = px / (size_t)W, x = px - y * (size_t)W;
+    dst[i] = (int8_t)(src[(y * (size_t)Wp + x) * 16 + (i & 15)] ^ 0x80u);
 }
 
 __global__ void k_keys_to_index(const unsigned long long* __restrict__ keys, int32_t* __restrict__ dst, int n)
@@ -1726,9 +1735,10 @@ void launch_sparse(const PairDev* d, int npairs, int eps2, int s, int maxW, int 
     const int nbx = (maxW + 2) / 3, nby = (maxH + 2) / 3;
     hipLaunchKernelGGL(k_sparse, dim3((nbx + 255) / 256, nby, 2 * npairs), dim3(256), 0, st, d, eps2, s);
 }
-void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, size_t n, hipStream_t st)
+void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, int W, int H, int Wp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_copy_desc_signed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+    const size_t n = (size_t)W * H * 16;
+    hipLaunchKernelGGL(k_copy_desc_signed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, W, H, Wp);
 }
 void launch_keys_to_index(const unsigned long long* keys, int32_t* dst, int n, hipStream_t st)
 {

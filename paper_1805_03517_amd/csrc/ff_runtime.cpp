@@ -42,7 +42,7 @@ void launch_to_quarter(const PairDev*, int, int, hipStream_t);
 void launch_sparse(const PairDev*, int, int, int, int, int, hipStream_t);
 void launch_save_state(const PairDev*, int, int, hipStream_t);
 void launch_fb2(const PairDev*, int, int, int, int, hipStream_t);
-void launch_copy_desc_signed(const uint8_t*, int8_t*, size_t, hipStream_t);
+void launch_copy_desc_signed(const uint8_t*, int8_t*, int, int, int, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
 }  // namespace ff
 
@@ -160,11 +160,12 @@ PairPlan plan_pair(const ff_params& p, int W, int H)
     for (int l = 0; l < p.levels; ++l) {
         pl.W[l] = l == 0 ? W : pl.W[l - 1] >> 1;
         pl.H[l] = l == 0 ? H : pl.H[l - 1] >> 1;
-        const size_t n = (size_t)pl.W[l] * pl.H[l], nT = (size_t)pl.W[l] * padded_height(pl.H[l]);
+        const size_t n = (size_t)pl.W[l] * pl.H[l], nT = (size_t)pl.W[l] * padded_height(pl.H[l]),
+                     nR = (size_t)padded_width(pl.W[l]) * pl.H[l];
         b += 2 * align_up(n);            // gray planes
-        b += 2 * align_up(n * 16) + 2 * align_up(nT * 16);   // descriptors, row- and column-major
-        b += 2 * align_up((size_t)padded_width(pl.W[l]) * pl.H[l] * 8) + 2 * align_up(n * 8);   // state, both layouts
-        if (p.flags & FF_COST_CENSUS) b += 2 * align_up(n * 8) + 2 * align_up(nT * 8);   // Census strings
+        b += 2 * align_up(nR * 16) + 2 * align_up(nT * 16);   // descriptors, row- and column-major
+        b += 2 * align_up(nR * 8) + 2 * align_up(n * 8);      // state, row- and column-major
+        if (p.flags & FF_COST_CENSUS) b += 2 * align_up(nR * 8) + 2 * align_up(nT * 8);   // Census strings
     }
     const int c = p.levels - 1;
     pl.nsx = (pl.W[c] + p.seed_stride - 1) / p.seed_stride;
@@ -282,12 +283,13 @@ void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& t
             L.Wp = padded_width(pl.W[l]);
             const size_t npT = (size_t)L.W * L.Hp;
             for (int k = 0; k < 2; ++k) L.gray[k] = (uint8_t*)take(np);
-            for (int k = 0; k < 2; ++k) L.desc[k] = (uint8_t*)take(np * 16);
+            const size_t npR = (size_t)L.Wp * L.H;                 // row-major planes, rows Wp apart
+            for (int k = 0; k < 2; ++k) L.desc[k] = (uint8_t*)take(npR * 16);
             for (int k = 0; k < 2; ++k) L.descT[k] = (uint8_t*)take(npT * 16);
-            for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take((size_t)L.Wp * L.H * 8);
+            for (int k = 0; k < 2; ++k) L.state[k] = (int2*)take(npR * 8);
             for (int k = 0; k < 2; ++k) L.stateT[k] = (int2*)take(np * 8);
             if (p.flags & FF_COST_CENSUS) {
-                for (int k = 0; k < 2; ++k) L.cen[k] = (uint8_t*)take(np * 8);
+                for (int k = 0; k < 2; ++k) L.cen[k] = (uint8_t*)take(npR * 8);
                 for (int k = 0; k < 2; ++k) L.cenT[k] = (uint8_t*)take(npT * 8);
             }
         }
@@ -451,12 +453,15 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
         for (int l = 0; l < L; ++l) FF_TRACED(KN_CENSUS, l, launch_census(d, n, l, D.maxW[l], D.maxH[l], st));
     if (stop.active && stop.st.kind == FF_STAGE_CENSUS) {
         const int l = stop.st.level;
-        FF_HIP(h, hipMemcpyAsync(stop.dst, tab0->lv[l].cen[stop.st.image], level_px(l) * 8, hipMemcpyDeviceToDevice, st));
+        const LevelDev& V = tab0->lv[l];
+        FF_HIP(h, hipMemcpy2DAsync(stop.dst, (size_t)V.W * 8, V.cen[stop.st.image], (size_t)V.Wp * 8, (size_t)V.W * 8,
+                                   (size_t)V.H, hipMemcpyDeviceToDevice, st));
         return FF_OK;
     }
     if (stop.active && stop.st.kind == FF_STAGE_DESC) {
         const int l = stop.st.level;
-        launch_copy_desc_signed(tab0->lv[l].desc[stop.st.image], (int8_t*)stop.dst, level_px(l) * 16, st);
+        const LevelDev& V = tab0->lv[l];
+        launch_copy_desc_signed(V.desc[stop.st.image], (int8_t*)stop.dst, V.W, V.H, V.Wp, st);
         return FF_OK;
     }
     FF_TRACED(KN_SEED_REC, c, launch_seed_records(d, n, c, D.maxPx[c], st));
