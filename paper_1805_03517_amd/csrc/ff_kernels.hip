@@ -103,9 +103,8 @@ __device__ __forceinline__ int3 xcd_block3()
 // columns are CS entries apart (CS = the level's Hp): W or H rounded up so
 // that every line of the plane starts on a 128-byte line.
 template <bool COL>
-__device__ __forceinline__ size_t pix(int x, int y, int W, int CS)
+__device__ __forceinline__ size_t pix(int x, int y, int CS)
 {
-    (void)W;
     return COL ? (size_t)x * CS + y : (size_t)y * CS + x;
 }
 
@@ -172,8 +171,8 @@ __device__ __forceinline__ int32_t subpix_cost(gcu8* __restrict__ DB, int W, int
     const int ix = tx >> 2, iy = ty >> 2, ax = tx & 3, ay = ty & 3;
     if (ix > W - 1 || iy > H - 1 || (ix == W - 1 && ax) || (iy == H - 1 && ay)) return kInf;
     const int ix1 = ax ? ix + 1 : ix, iy1 = ay ? iy + 1 : iy;
-    const uint4 b00 = ld16(DB + pix<COL>(ix, iy, W, CS) * 16), b10 = ld16(DB + pix<COL>(ix1, iy, W, CS) * 16);
-    const uint4 b01 = ld16(DB + pix<COL>(ix, iy1, W, CS) * 16), b11 = ld16(DB + pix<COL>(ix1, iy1, W, CS) * 16);
+    const uint4 b00 = ld16(DB + pix<COL>(ix, iy, CS) * 16), b10 = ld16(DB + pix<COL>(ix1, iy, CS) * 16);
+    const uint4 b01 = ld16(DB + pix<COL>(ix, iy1, CS) * 16), b11 = ld16(DB + pix<COL>(ix1, iy1, CS) * 16);
     const uint32_t w00 = (4 - ax) * (4 - ay), w10 = ax * (4 - ay), w01 = (4 - ax) * ay, w11 = ax * ay;
     const uint4 i = make_uint4(bilerp_word(b00.x, b10.x, b01.x, b11.x, w00, w10, w01, w11),
                                bilerp_word(b00.y, b10.y, b01.y, b11.y, w00, w10, w01, w11),
@@ -194,7 +193,7 @@ __device__ __forceinline__ int32_t feat_cost(gcu8* __restrict__ DB, int W, int H
     } else {
         const int qx = x + flow_x(f), qy = y + flow_y(f);
         if ((unsigned)qx >= (unsigned)W || (unsigned)qy >= (unsigned)H) return kInf;
-        return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, W, CS)));
+        return Feat<CK>::dist(a, Feat<CK>::load(DB, pix<COL>(qx, qy, CS)));
     }
 }
 
@@ -647,7 +646,7 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     const PairDev& P = pairs[blockIdx.z >> 1];
     const int dir = blockIdx.z & 1;
     const LevelDev& L = P.lv[level];
-    const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
+    const int N = L.W * L.H, Q = P.nsx * P.nsy;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (blockIdx.x * 4 * 16 * MQ >= Q) return;                   // no seeds in this block: uniform
     const int ntiles = (N + 15) >> 4;
@@ -1052,7 +1051,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                     // running best's upper bound: never selected, not gathered
                     const bool in = (unsigned)qx < (unsigned)W && (unsigned)qy < (unsigned)H && (qdx | qdy) != 0;
                     pin[c] |= in ? (1u << j) : 0u;
-                    pdesc[c][j] = in ? Feat<CK>::load(DB, pix<COL>(qx, qy, W, CS)) : Feat<CK>::zero();
+                    pdesc[c][j] = in ? Feat<CK>::load(DB, pix<COL>(qx, qy, CS)) : Feat<CK>::zero();
                 }
             }
             pend = true;
@@ -1309,7 +1308,7 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                             const int ri = (COL ? qy : qx) - si0, rj = (COL ? qx : qy) - sj0;
                             if ((unsigned)ri < (unsigned)RI && (unsigned)rj < (unsigned)RJ)
                                 return sad16(ac, region[rj * RI + ri]);
-                            return sad16(ac, ld16(DB + pix<COL>(qx, qy, W, CS) * 16));
+                            return sad16(ac, ld16(DB + pix<COL>(qx, qy, CS) * 16));
                         });
                     } else {
                         random_search<RC>(bf, bc, W, x, y, rlev, ctr2, sc,
