@@ -919,3 +919,108 @@ def test_subpix_refinement_end_to_end(orc):
     err_int = np.abs(4 * ri["flow_f"][inner][..., 0].astype(np.int32) + 2)
     err_sub = np.abs(rs["flow_f"][inner][..., 0].astype(np.int32) + 2)
     assert err_int.mean() == 2.0 and err_sub.mean() < 0.5
+
+
+# ------------------------------------------ quarter-pixel consistency --
+def _load_quarter_fixture():
+    """Parse tests/golden/fb_error_quarter_px.txt: three fields of
+    "Fx,Fy,cost" triples and the two expected error planes."""
+    path = os.path.join(HERE, "golden", "fb_error_quarter_px.txt")
+    blocks, name = {}, None
+    for raw in open(path):
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        if line in ("F", "B1", "B2", "E1", "E2"):
+            name = line
+            blocks[name] = []
+            continue
+        blocks[name].append(line.split())
+    inf = 2**31 - 1
+
+    def num(s):
+        return inf if s == "INF" else int(s)
+
+    fields = {}
+    for k in ("F", "B1", "B2"):
+        rows = [[[num(v) for v in cell.split(",")] for cell in row] for row in blocks[k]]
+        a = np.array(rows, dtype=np.int64)
+        fields[k] = (a[..., :2].astype(np.int16), a[..., 2].astype(np.int32))
+    errs = {k: np.array([[num(v) for v in row] for row in blocks[k]], dtype=np.int64).astype(np.int32)
+            for k in ("E1", "E2")}
+    return fields, errs
+
+
+def _check_quarter_fixture(mod):
+    fields, errs = _load_quarter_fixture()
+    (F, cF), (B1, cB1), (B2, cB2) = fields["F"], fields["B1"], fields["B2"]
+    e1 = mod.fb_error(F, cF, B1, cB1, unit=4)
+    e2 = mod.fb_error2(F, cF, B1, cB1, B2, cB2, unit=4)
+    return np.array_equal(e1, errs["E1"]) and np.array_equal(e2, errs["E2"]), e1, e2
+
+
+def test_fb_error_quarter_pixel_worked_example(orc):
+    """Sec. 3.1 consistency check on quarter-pixel flows (the bilinear
+    sub-pixel matches): the hand-worked fixture fixes the rounding of the
+    target to whole pixels (half up, also for negative flows), the first and
+    last columns as targets, INF from the own match and from either inverse
+    field, the error unit (1/16 px^2) and the two-check maximum."""
+    ok, e1, e2 = _check_quarter_fixture(orc)
+    _, errs = _load_quarter_fixture()
+    assert np.array_equal(e1, errs["E1"]), e1
+    assert np.array_equal(e2, errs["E2"]), e2
+    # the threshold of eps = 1 px is 16 in these units: exactly the error 16 at (1, 2) is kept
+    assert ((e1 <= 16).astype(np.uint8)).tolist() == [[0, 0, 0, 0, 1, 0, 0, 0], [0, 0, 0, 1, 0, 0, 0, 0],
+                                                       [0, 1, 0, 0, 1, 0, 0, 0]]
+    assert ok
+
+
+# Misreadings of the rounding a plausible implementation could make; each is
+# planted in a scratch copy of the oracle, which must then fail the fixture.
+_ROUNDING_MUTANTS = {
+    "truncating division": "static int floor_div(int v, int d) { return v / d; }",
+    "half down": "static int floor_div(int v, int d) { return v >= 1 ? (v - 1) / d : -((-(v - 1) + d - 1) / d); }",
+    "half away from zero": ("static int floor_div(int v, int d) { int t = v - d / 2; "
+                            "return t >= 0 ? v / d : -((-t + d / 2) / d); }"),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(_ROUNDING_MUTANTS))
+def test_fb_error_quarter_fixture_rejects_misrounded_oracles(orc, tmp_path, mutant):
+    import importlib.util
+
+    src = open(os.path.join(os.path.dirname(HERE), "oracle", "ff_oracle.c")).read()
+    orig = "static int floor_div(int v, int d) { return v >= 0 ? v / d : -((-v + d - 1) / d); }"
+    assert src.count(orig) == 1
+    mutated = src.replace(orig, _ROUNDING_MUTANTS[mutant])
+    csrc = tmp_path / "ff_oracle.c"
+    csrc.write_text(mutated)
+    so = tmp_path / "libff_oracle.so"
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-shared", "-fPIC", "-I" + os.path.join(os.path.dirname(HERE), "oracle"),
+                           str(csrc), "-o", str(so)])
+    spec = importlib.util.spec_from_file_location(f"oracle_mutant_{abs(hash(mutant))}",
+                                                  os.path.join(os.path.dirname(HERE), "oracle", "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod._LIB = str(so)
+    mod._lib = None
+    ok, _, _ = _check_quarter_fixture(mod)
+    assert not ok, f"a {mutant} oracle passes the quarter-pixel fixture"
+
+
+def test_cost_is_elementwise_sad(orc):
+    """Sec. 3.1 matching cost over the descriptors, read as the sum of
+    absolute differences: element by element against numpy's |a - b|.sum()
+    (a sum of squares, a dropped coefficient or a swapped operand fails)."""
+    rng = np.random.default_rng(41)
+    DA = rng.integers(-128, 128, size=(6, 11, 16), dtype=np.int8)
+    DB = rng.integers(-128, 128, size=(6, 11, 16), dtype=np.int8)
+    DB[2, 5] = DA[1, 3]
+    DB[2, 5, 7] = np.int8(-128) if DA[1, 3, 7] >= 0 else np.int8(127)   # one large coefficient apart
+    for _ in range(300):
+        x, y = int(rng.integers(0, 11)), int(rng.integers(0, 6))
+        fx, fy = int(rng.integers(-x, 11 - x)), int(rng.integers(-y, 6 - y))
+        ref = int(np.abs(DA[y, x].astype(np.int64) - DB[y + fy, x + fx].astype(np.int64)).sum())
+        assert orc.cost(DA, DB, x, y, fx, fy) == ref
+    single = abs(int(DA[1, 3, 7]) - int(DB[2, 5, 7]))
+    assert orc.cost(DA, DB, 3, 1, 2, 1) == single and single >= 128
