@@ -38,9 +38,16 @@
  * tables), allocated on first use for a shape/batch and reused after.
  * Calls are stream-ordered: they validate synchronously, enqueue the work on
  * `stream` (a hipStream_t, or NULL for the null stream) and return; outputs
- * are valid once the stream reaches that point.  A handle must not be used
- * from two threads at once.  Errors of already-enqueued work surface as
- * FF_ERR_HIP on a later call.
+ * are valid once the stream reaches that point.  Calls on one handle share
+ * its workspace, so a call on a different stream than the handle's previous
+ * call first makes its stream wait for that call's work (an event): calls
+ * on one handle never overlap on the device, whatever their streams.  A
+ * handle must not be used from two threads at once.  Errors of
+ * already-enqueued work surface as FF_ERR_HIP on a later call.
+ *
+ * Budget: params.hbm_budget caps the device memory a handle holds -- its
+ * own workspace (ff_match_pair / ff_match_batch) and its serving lanes
+ * together.
  */
 #ifndef FF_H
 #define FF_H
@@ -131,33 +138,62 @@ typedef struct {
     uint8_t* sparse_bwd;
 } ff_pair;
 
-/* Create a handle on HIP device `device` (must be gfx950).  Copies *params;
- * FF_ERR_INVALID for a parameter outside the ranges above, an unknown flag,
- * or FF_SUBPIXEL together with FF_COST_CENSUS. */
+/* Create a handle on HIP device `device` (must be gfx950) for the search
+ * parameters of Sec. 3.1 (pyramid depth, seed grid, iterations, random-search
+ * radius, consistency threshold epsilon and sparsification minimum s of
+ * Table 3).  Copies *params; allocates no device workspace yet (the first
+ * call sizes it).  FF_ERR_INVALID for a NULL argument, a device index out of
+ * range, a parameter outside the ranges above, an unknown flag, or
+ * FF_SUBPIXEL together with FF_COST_CENSUS; FF_ERR_UNSUPPORTED on another
+ * architecture; FF_ERR_HIP when the runtime fails.  *out is NULL on error;
+ * on success the caller owns the handle until ff_destroy. */
 ff_status ff_create(const ff_params* params, int device, ff_handle* out);
 
-/* Match one pair (the whole search above) on `stream`. */
+/* Match one pair on `stream`: the matching of Sec. 3.1 from the two frames
+ * to the outputs of ff_pair -- luma, pyramid, descriptors, exact initial
+ * matches at the coarsest level, per level the initialisation and `iters`
+ * rounds of propagation in four directions with random search, optionally
+ * the quarter-pixel refinement, then the forward-backward consistency check
+ * (threshold epsilon, Table 3), optionally the second check and the 3x3
+ * sparsification.  All pointers of *pair are caller-owned device memory
+ * that must stay valid until the stream has passed the call.
+ * FF_ERR_INVALID for a NULL or malformed pair (see ff_pair), FF_ERR_BUDGET
+ * when the workspace would exceed the budget, FF_ERR_OOM when the device
+ * allocation fails, FF_ERR_HIP when the runtime fails; nothing is enqueued
+ * then.  The handle's workspace grows to the largest call and is kept. */
 ff_status ff_match_pair(ff_handle h, const ff_pair* pair, void* stream);
 
-/* Match n independent pairs, of any sizes, in one grouped pass: every stage
- * runs once over all pairs.  Outputs are bit-identical to n calls of
- * ff_match_pair.  1 <= n <= 32767. */
+/* Match n independent pairs, of any sizes, in one grouped pass (the search
+ * of Sec. 3.1 on every pair): every stage runs once over all pairs.
+ * Outputs are bit-identical to n calls of ff_match_pair.  1 <= n <= 32767;
+ * errors as ff_match_pair (the first invalid pair rejects the batch and
+ * nothing is enqueued). */
 ff_status ff_match_batch(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
 
-/* Synchronise the handle's device and free everything it owns. */
+/* Synchronise the handle's device and free everything it owns (workspace,
+ * serving lanes, graphs, events).  NULL is ignored.  Not part of the method:
+ * resource management. */
 void ff_destroy(ff_handle h);
 
 /* Message of the last non-OK status on this handle (static string when h is
- * NULL).  Valid until the next call on the handle. */
+ * NULL).  Valid until the next call on the handle.  Not part of the method. */
 const char* ff_last_error(ff_handle h);
 
-/* Bytes of device workspace a batch of these pairs needs (no allocation). */
+/* Bytes of device workspace a batch of these pairs needs (no allocation):
+ * the pyramids, descriptor planes, search state and seed tables of Sec. 3.1
+ * for every pair; only width, height and channels of each pair are read.
+ * 0 for a NULL handle or pairs, or n < 1. */
 uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
 
 /* ---- serving: continuous batching --------------------------------------
+ * Deployment of the search of Sec. 3.1 as a request loop; the arithmetic of
+ * every pair is that of ff_match_pair.
  * The handle keeps `lanes` concurrent cohorts, each on its own HIP stream
  * with its own preallocated workspace of `lane_bytes` bytes (lanes x
- * lane_bytes must fit params.hbm_budget when a budget is set).  ff_submit
+ * lane_bytes, plus the handle's own workspace, must fit params.hbm_budget
+ * when a budget is set: ff_serve_config releases the handle's own workspace
+ * when both do not fit, and a later ff_match_* regrows it within what the
+ * lanes leave, or fails with FF_ERR_BUDGET).  ff_submit
  * queues one pair (FIFO) and returns at once; whenever a lane is idle, the
  * queued pairs at the head that fit its workspace start as one grouped
  * batch on that lane, overlapping with the cohorts running on the others.
@@ -181,6 +217,7 @@ int32_t   ff_poll(ff_handle h, uint64_t* tags_done, int32_t max);
 int32_t   ff_serve_inflight(ff_handle h);
 
 /* ---- schedule autotuning -----------------------------------------------
+ * Scheduling of the propagation and random search of Sec. 3.1 only.
  * The row and column phases run one wave per image line and solve each
  * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves; with
  * `staged` = 1 the waves of a block take their windows in lockstep and read
@@ -219,7 +256,8 @@ typedef struct {
 ff_status ff_profile_enable(ff_handle h, int32_t on);
 int32_t   ff_profile_read(ff_handle h, ff_profile_entry* out, int32_t max);
 
-/* ---- intermediates, for parity tests against an independent CPU model ---- */
+/* ---- intermediates, for parity tests against an independent CPU model ----
+ * Each stage names a step of Sec. 3.1 in the order the search takes them. */
 typedef enum {
     FF_STAGE_GRAY = 0,      /* image `image` level-0 luma: [H][W] uint8               */
     FF_STAGE_PYRAMID = 1,   /* image `image` level `level`: [H_l][W_l] uint8          */

@@ -75,6 +75,12 @@ struct ff_ctx {
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
     std::vector<PairDev> last;       // what d_table holds now
+    // stream ordering between calls: every call records run_done on its
+    // stream, and a call on another stream first waits for it, since all
+    // calls share the arena and the device table
+    hipEvent_t run_done = nullptr;
+    hipStream_t run_stream = nullptr;
+    bool run_any = false;
     // tracing: event pairs around every launch while enabled
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -220,12 +226,17 @@ ff_status validate_pair(ff_ctx* h, const ff_pair& q)
     return FF_OK;
 }
 
+// Bytes the handle's serving lanes hold (0 when serving is not configured).
+size_t serve_bytes(const ff_ctx* h);
+
 ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
 {
-    if (h->prm.hbm_budget && need > h->prm.hbm_budget) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "workspace of %zu bytes exceeds the budget of %llu bytes", need,
-                 (unsigned long long)h->prm.hbm_budget);
+    // one budget per handle: its own arena and its serving lanes together
+    const size_t lanes = serve_bytes(h);
+    if (h->prm.hbm_budget && need + lanes > h->prm.hbm_budget) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "workspace of %zu bytes (plus %zu held by serving lanes) exceeds the budget of %llu bytes",
+                 need, lanes, (unsigned long long)h->prm.hbm_budget);
         return fail(h, FF_ERR_BUDGET, buf);
     }
     if (need <= h->arena_bytes) return FF_OK;
@@ -236,7 +247,8 @@ ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
         h->arena_bytes = 0;
         h->last.clear();
     }
-    const size_t want = exact ? need : need + need / 8;     // head-room against regrowth
+    size_t want = exact ? need : need + need / 8;           // head-room against regrowth
+    if (h->prm.hbm_budget) want = std::min<size_t>(want, h->prm.hbm_budget - lanes);
     hipError_t e = hipMalloc(&h->arena, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -253,13 +265,11 @@ ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
     return FF_OK;
 }
 
-// Fill the per-pair table: carve each pair's buffers out of the arena.
-void build_table(ff_ctx* h, const ff_pair* pairs, int n, std::vector<PairDev>& tab,
-                 std::vector<PairPlan>& plans)
+// Fill the per-pair table: carve each pair's buffers out of the workspace
+// at `base`.
+void build_table(const ff_params& p, char* base, const ff_pair* pairs, int n, PairDev* tab, const PairPlan* plans)
 {
-    const ff_params& p = h->prm;
-    tab.assign(n, PairDev{});
-    char* base = (char*)h->arena;
+    for (int i = 0; i < n; ++i) tab[i] = PairDev{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* r = base + off;
@@ -641,8 +651,11 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     FF_HIP(h, hipSetDevice(h->device));
     ff_status s = ensure_arena(h, need);
     if (s != FF_OK) return s;
-    std::vector<PairDev> tab;
-    build_table(h, pairs, n, tab, plans);
+    // the previous call may still run on another stream: this call reuses
+    // its arena and device table, so it starts after it
+    if (h->run_any && st != h->run_stream) FF_HIP(h, hipStreamWaitEvent(st, h->run_done, 0));
+    std::vector<PairDev> tab(n);
+    build_table(p, (char*)h->arena, pairs, n, tab.data(), plans.data());
     s = upload_table(h, tab, st);
     if (s != FF_OK) return s;
 
@@ -662,6 +675,9 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
         s = enqueue(h, h->d_table, D, st, stop, &tab[0], &plans[0]);
     if (s != FF_OK) return s;
     FF_HIP(h, hipGetLastError());
+    FF_HIP(h, hipEventRecord(h->run_done, st));
+    h->run_stream = st;
+    h->run_any = true;
     return FF_OK;
 }
 
@@ -768,6 +784,8 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
     return FF_OK;
 }
 
+void free_ctx(ff_ctx* h);
+
 ff_ctx* make_ctx(const ff_params& p, int device)
 {
     ff_ctx* h = new ff_ctx;
@@ -784,12 +802,20 @@ ff_ctx* make_ctx(const ff_params& p, int device)
             return nullptr;
         }
     }
+    // the staging ring starts with room for 16 pairs per slot
+    bool ok = hipEventCreateWithFlags(&h->run_done, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < ff_ctx::kStaging; ++k) {
+        ok = hipHostMalloc((void**)&h->h_table[k], 16 * sizeof(PairDev), hipHostMallocDefault) == hipSuccess;
+        if (ok) h->h_table_cap[k] = 16;
+    }
+    if (!ok) {
+        free_ctx(h);
+        return nullptr;
+    }
     const char* g = std::getenv("FF_GRAPHS");
     h->use_graphs = !(g && g[0] == '0');
     return h;
 }
-
-void free_ctx(ff_ctx* h);
 
 void free_serve(ff_ctx* h)
 {
@@ -824,8 +850,14 @@ void free_ctx(ff_ctx* h)
         (void)hipGraphDestroy(e.graph);
     }
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->run_done) (void)hipEventDestroy(h->run_done);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
+}
+
+size_t serve_bytes(const ff_ctx* h)
+{
+    return h->serve ? h->serve->lanes.size() * h->serve->lane_bytes : 0;
 }
 
 ff_status serve_configure(ff_ctx* h, int lanes, size_t lane_bytes)
@@ -841,6 +873,16 @@ ff_status serve_configure(ff_ctx* h, int lanes, size_t lane_bytes)
         free_serve(h);
     }
     FF_HIP(h, hipSetDevice(h->device));
+    // one budget per handle: when the handle's own arena and the lanes do not
+    // fit together, the arena is released (ff_match_* regrows it within what
+    // the lanes leave)
+    if (h->prm.hbm_budget && h->arena && (uint64_t)lanes * lane_bytes + h->arena_bytes > h->prm.hbm_budget) {
+        FF_HIP(h, hipDeviceSynchronize());
+        FF_HIP(h, hipFree(h->arena));
+        h->arena = nullptr;
+        h->arena_bytes = 0;
+        h->last.clear();
+    }
     ServeState* sv = new ServeState;
     h->serve = sv;
     sv->lane_bytes = lane_bytes;

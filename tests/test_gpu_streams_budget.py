@@ -1,0 +1,114 @@
+"""Calls on one handle from two streams, and one HBM budget per handle.
+
+Both are properties of the C ABI's runtime (include/ff.h: stream ordering,
+budget), checked through the HIP path against the CPU oracle bit for bit.
+Each GPU step prints the case it runs first."""
+import numpy as np
+import pytest
+
+from paper_1805_03517_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU test run without a visible GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ffm():
+    from paper_1805_03517_amd import ff
+    return ff
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _same(ref, got, tag):
+    for k in ("flow_f", "cost_f", "mask_f", "flow_b", "cost_b", "mask_b"):
+        g = got[k].cpu().numpy()
+        if not np.array_equal(g, ref[k]):
+            raise AssertionError(f"{tag}: {k} differs at {int((g != ref[k]).sum())} places")
+
+
+def test_two_streams_on_one_handle(torch, ffm, orc):
+    """A large batch on one stream and, right after it with no host sync, a
+    batch of other pairs on a second stream: the second call reuses the
+    handle's workspace and device table, so it must start after the first.
+    Both batches are compared with the oracle."""
+    big = [synth.config1(seed=300 + k)[:2] for k in range(4)]
+    rng = np.random.default_rng(301)
+    small = []
+    for k in range(6):
+        W, H = int(rng.integers(96, 200)), int(rng.integers(96, 160))
+        d = (int(rng.integers(-12, 13)), int(rng.integers(-12, 13)))
+        small.append(synth.translated_pair(np.random.default_rng(310 + k), W, H, d=d)[:2])
+    m = ffm.Matcher(levels=3)
+    dbig = [(_dev(torch, a), _dev(torch, b)) for a, b in big]
+    dsmall = [(_dev(torch, a), _dev(torch, b)) for a, b in small]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    for rep in range(2):                        # the second round replays captured graphs
+        say("two streams, round", rep, ": 4 x 1242x375 RGB on s1, then 6 small gray pairs on s2")
+        with torch.cuda.stream(s1):
+            ob = m.match_batch(dbig)
+        with torch.cuda.stream(s2):
+            osm = m.match_batch(dsmall)
+        torch.cuda.synchronize()
+        p = orc.params(levels=3)
+        for k, (a, b) in enumerate(small):
+            _same(orc.match(a, b, p), osm[k], f"round {rep} small member {k}")
+        for k in (0, 3):
+            _same(orc.match(big[k][0], big[k][1], p), ob[k], f"round {rep} big member {k}")
+    m.close()
+
+
+def test_budget_covers_arena_and_serving_lanes(torch, ffm):
+    """params.hbm_budget caps the handle's own workspace and its serving
+    lanes together: with a budget that holds one of the two, configuring the
+    lanes releases the arena, and matching then fails with FF_ERR_BUDGET."""
+    i1, i2, _ = synth.config0()                       # 128 x 96 gray
+    img, img2 = _dev(torch, i1), _dev(torch, i2)
+    probe = ffm.Matcher(levels=3)
+    need = probe.workspace_bytes([(96, 128, 1)])
+    probe.close()
+    say("budget: arena then lanes, pair needs", need)
+    m = ffm.Matcher(levels=3, hbm_budget=2 * need)
+    m.match(img, img2)                                  # the arena fits the budget alone
+    torch.cuda.synchronize()
+    m.serve_config(lanes=1, lane_bytes=(3 * need) // 2)  # fits alone; the arena is released
+    with pytest.raises(ffm.FFError) as e:
+        m.match(img, img2)                              # arena + lanes > budget
+    assert e.value.status == ffm.FF_ERR_BUDGET
+    o = m.submit(img, img2, tag=7)                     # the lanes still serve
+    import time
+    t0 = time.time()
+    got = []
+    while not got and time.time() - t0 < 60:
+        got = m.poll()
+    assert got == [7]
+    ref = probe_ref = ffm.Matcher(levels=3)
+    want = ref.match(img, img2)
+    torch.cuda.synchronize()
+    for k in want:
+        assert torch.equal(want[k], o[k]), k
+    probe_ref.close()
+    m.close()
+    say("budget: lanes then arena")
+    m = ffm.Matcher(levels=3, hbm_budget=3 * need)
+    m.serve_config(lanes=2, lane_bytes=need)
+    m.match(img, img2)                                  # 2 need + need fits
+    torch.cuda.synchronize()
+    with pytest.raises(ffm.FFError) as e:
+        m.serve_config(lanes=3, lane_bytes=need + 1)   # the lanes alone exceed the budget
+    assert e.value.status == ffm.FF_ERR_BUDGET
+    m.close()
