@@ -170,6 +170,22 @@ ff_status ff_match_pair(ff_handle h, const ff_pair* pair, void* stream);
  * nothing is enqueued). */
 ff_status ff_match_batch(ff_handle h, const ff_pair* pairs, int32_t n, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search and bit-identical outputs as ff_match_pair, with the pair's whole
+ * workspace in a fixed scratch array of 128 MiB per device inside the
+ * library (reserved when the library's code is loaded on a device; a
+ * 1242 x 375 pair with every flag needs about 92 MB).  It calls no
+ * hipMalloc, hipFree or pinned-memory allocation, captures no graph and
+ * records no tracing events.  Calls on one device share the array, which
+ * keeps the last call's contents (every buffer is written before it is
+ * read); they are ordered through an event, so calls on different streams,
+ * handles or host threads of one process run one after the other on the
+ * device rather than racing.  FF_ERR_BUDGET when the pair needs more than
+ * the array holds (ff_workspace_bytes of the pair + 1 KiB of table); other
+ * errors as ff_match_pair. */
+ff_status ff_match_pair_noalloc(ff_handle h, const ff_pair* pair, void* stream);
+
 /* Synchronise the handle's device and free everything it owns (workspace,
  * serving lanes, graphs, events).  NULL is ignored.  Not part of the method:
  * resource management. */

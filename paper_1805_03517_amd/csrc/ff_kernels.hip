@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "ff_internal.h"
 
 namespace ff {
@@ -1543,6 +1545,66 @@ __global__ void k_keys_to_index(const unsigned long long* __restrict__ keys, int
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) dst[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)keys[i]);
 }
+
+// ------------------------------------------- allocation-free scratch ----
+// Workspace of ff_match_pair_noalloc: one pair's pyramids, descriptors,
+// search state and seed tables plus its device table, in a fixed array that
+// every GPU the library runs on holds until the process ends.  In host code
+// the array's name is only a stand-in for the device address: the address
+// comes from hipGetSymbolAddress, taken once per device (with that device
+// current) when a handle is created there, and only that address is handed
+// to kernels and copies.  Calls on one device are ordered through an event
+// recorded after each call (the next call's stream waits for it) under a
+// host lock, so calls from several streams, handles or threads never use the
+// array at the same time.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_setup;
+std::mutex g_scratch_use[kNoAllocDevices];
+void* g_scratch_ptr[kNoAllocDevices];
+hipEvent_t g_scratch_done[kNoAllocDevices];
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+// Once per device, with `device` current: the array's device address and
+// the event that orders the calls using it.
+hipError_t noalloc_setup(int device)
+{
+    if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_setup);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    g_scratch_done[device] = ev;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+bool noalloc_lookup(int device, void** ptr, hipEvent_t* done)
+{
+    if (device < 0 || device >= kNoAllocDevices) return false;
+    std::lock_guard<std::mutex> g(g_scratch_setup);
+    *ptr = g_scratch_ptr[device];
+    *done = g_scratch_done[device];
+    return *ptr != nullptr;
+}
+
+void noalloc_lock(int device) { g_scratch_use[device].lock(); }
+void noalloc_unlock(int device) { g_scratch_use[device].unlock(); }
 
 // ------------------------------------------------------------ launchers --
 #define FF_GRID1(n) dim3((unsigned)(((n) + 255) / 256))

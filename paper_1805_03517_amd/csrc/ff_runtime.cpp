@@ -44,6 +44,11 @@ void launch_save_state(const PairDev*, int, int, hipStream_t);
 void launch_fb2(const PairDev*, int, int, int, int, hipStream_t);
 void launch_copy_desc_signed(const uint8_t*, int8_t*, int, int, int, hipStream_t);
 void launch_keys_to_index(const unsigned long long*, int32_t*, int, hipStream_t);
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_setup(int device);
+bool noalloc_lookup(int device, void** ptr, hipEvent_t* done);
+void noalloc_lock(int device);
+void noalloc_unlock(int device);
 }  // namespace ff
 
 using namespace ff;
@@ -266,7 +271,7 @@ ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
 }
 
 // Fill the per-pair table: carve each pair's buffers out of the workspace
-// at `base`.
+// at `base` (the handle's arena, or the allocation-free path's scratch).
 void build_table(const ff_params& p, char* base, const ff_pair* pairs, int n, PairDev* tab, const PairPlan* plans)
 {
     for (int i = 0; i < n; ++i) tab[i] = PairDev{};
@@ -681,6 +686,73 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     return FF_OK;
 }
 
+// The allocation-free form of ff_match_pair: the pair's workspace and its
+// device table live in the library's static per-device scratch array (set up
+// by ff_create), the launches are enqueued directly (no graph capture, no
+// tracing events), and nothing is allocated -- neither device nor pinned
+// memory (the staging ring holds 16 pairs from creation).  Calls on one
+// device are ordered through the scratch's event: each waits on the stream
+// for the previous call's work, so calls from different streams or handles
+// never overlap on the array.
+ff_status run_noalloc(ff_ctx* h, const ff_pair* pair, hipStream_t st)
+{
+    const ff_params& p = h->prm;
+    ff_status s = validate_pair(h, *pair);
+    if (s != FF_OK) return s;
+    const PairPlan plan = plan_pair(p, pair->width, pair->height);
+    const size_t head = align_up(sizeof(PairDev));
+    const size_t cap = noalloc_scratch_bytes();
+    if (head + plan.bytes > cap) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "pair needs %zu bytes of workspace; the allocation-free entry point holds at most %zu",
+                 head + plan.bytes, cap);
+        return fail(h, FF_ERR_BUDGET, buf);
+    }
+    FF_HIP(h, hipSetDevice(h->device));
+    void* base = nullptr;
+    hipEvent_t done = nullptr;
+    if (!noalloc_lookup(h->device, &base, &done))
+        return fail(h, FF_ERR_HIP, "the allocation-free scratch of this device was not set up (ff_create)");
+    PairDev tab;
+    build_table(p, (char*)base + head, pair, 1, &tab, &plan);
+    Dims D;
+    D.n = 1;
+    for (int l = 0; l < p.levels; ++l) {
+        D.maxW[l] = plan.W[l];
+        D.maxH[l] = plan.H[l];
+        D.maxPx[l] = plan.W[l] * plan.H[l];
+    }
+    D.maxQ = plan.nsx * plan.nsy;
+    noalloc_lock(h->device);
+    s = FF_OK;
+    do {
+        hipError_t e = hipStreamWaitEvent(st, done, 0);
+        // the table goes through the handle's pinned staging ring (slot k is
+        // refilled only after the copy that last read it has finished)
+        const int k = (int)(h->staging_next++ % ff_ctx::kStaging);
+        if (e == hipSuccess) e = hipEventSynchronize(h->table_ev[k]);
+        if (e == hipSuccess) {
+            std::memcpy(h->h_table[k], &tab, sizeof(PairDev));
+            e = hipMemcpyAsync(base, h->h_table[k], sizeof(PairDev), hipMemcpyHostToDevice, st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(h->table_ev[k], st);
+        if (e != hipSuccess) {
+            s = hip_fail(h, e, "allocation-free table upload");
+            break;
+        }
+        const bool prof = h->prof_on;
+        h->prof_on = false;
+        s = enqueue(h, (const PairDev*)base, D, st, Stop{}, &tab, &plan);
+        h->prof_on = prof;
+        if (s != FF_OK) break;
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(done, st);
+        if (e != hipSuccess) s = hip_fail(h, e, "allocation-free launch");
+    } while (0);
+    noalloc_unlock(h->device);
+    return s;
+}
+
 struct Timed {
     int kernel, level;
     double ms;
@@ -802,7 +874,8 @@ ff_ctx* make_ctx(const ff_params& p, int device)
             return nullptr;
         }
     }
-    // the staging ring starts with room for 16 pairs per slot
+    // the staging ring starts with room for 16 pairs per slot, so a
+    // single-pair call never allocates pinned memory
     bool ok = hipEventCreateWithFlags(&h->run_done, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; ok && k < ff_ctx::kStaging; ++k) {
         ok = hipHostMalloc((void**)&h->h_table[k], 16 * sizeof(PairDev), hipHostMallocDefault) == hipSuccess;
@@ -971,8 +1044,18 @@ ff_status ff_create(const ff_params* params, int device, ff_handle* out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FF_ERR_UNSUPPORTED;
     ff_ctx* h = make_ctx(*params, device);
     if (!h) return FF_ERR_HIP;
+    // the allocation-free entry point's scratch on this device (once per
+    // device; a failure here surfaces only on that entry point)
+    (void)noalloc_setup(device);
     *out = h;
     return FF_OK;
+}
+
+ff_status ff_match_pair_noalloc(ff_handle h, const ff_pair* pair, void* stream)
+{
+    if (!h) return FF_ERR_INVALID;
+    if (!pair) return fail(h, FF_ERR_INVALID, "pair is NULL");
+    return run_noalloc(h, pair, (hipStream_t)stream);
 }
 
 ff_status ff_match_pair(ff_handle h, const ff_pair* pair, void* stream)

@@ -22,7 +22,7 @@ STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE, STAGE_CENSUS = 
 INF = 2**31 - 1
 
 # Every symbol include/ff.h declares, in declaration order.
-EXPORTS = ("ff_create", "ff_match_pair", "ff_match_batch", "ff_destroy", "ff_last_error",
+EXPORTS = ("ff_create", "ff_match_pair", "ff_match_batch", "ff_match_pair_noalloc", "ff_destroy", "ff_last_error",
            "ff_workspace_bytes", "ff_serve_config", "ff_submit", "ff_poll", "ff_serve_inflight",
            "ff_autotune", "ff_tune_get", "ff_tune_set", "ff_profile_enable", "ff_profile_read",
            "ff_debug_stage")
@@ -80,6 +80,8 @@ def lib():
         l.ff_match_pair.restype = ctypes.c_int
         l.ff_match_batch.argtypes = [vp, ctypes.POINTER(Pair), i32, vp]
         l.ff_match_batch.restype = ctypes.c_int
+        l.ff_match_pair_noalloc.argtypes = [vp, ctypes.POINTER(Pair), vp]
+        l.ff_match_pair_noalloc.restype = ctypes.c_int
         l.ff_destroy.argtypes = [vp]
         l.ff_destroy.restype = None
         l.ff_last_error.argtypes = [vp]
@@ -195,6 +197,15 @@ class Matcher:
         o = out if out is not None else self._outputs(H, W, bwd, cost)
         p = self._pair(img1, img2, o)
         self._check(lib().ff_match_pair(self._h, ctypes.byref(p), _stream_ptr(self._torch, self.device)))
+        return o
+
+    def match_noalloc(self, img1, img2, bwd=True, cost=True, out=None):
+        """ff_match_pair_noalloc: the same search in the library's fixed
+        per-device scratch (no device allocation by the library)."""
+        H, W = int(img1.shape[0]), int(img1.shape[1])
+        o = out if out is not None else self._outputs(H, W, bwd, cost)
+        p = self._pair(img1, img2, o)
+        self._check(lib().ff_match_pair_noalloc(self._h, ctypes.byref(p), _stream_ptr(self._torch, self.device)))
         return o
 
     def match_batch(self, pairs, bwd=True, cost=True, outs=None):
