@@ -63,32 +63,43 @@ COL_BYTES_PER_PX = 12 * 16 + 32
 INIT_BYTES_PER_PX = 8 + 16 + 16 + 8     # coarse state, own descriptor, candidate, state write
 
 
-def kernel_rooflines(prof, batch, steps):
-    """Every kernel of the step against HBM (algorithmic bytes per step /
-    its device time per step): what each step of the method must move, every
+def step_bytes(shapes, levels, iters=2):
+    """Algorithmic bytes per kernel of one pass over a batch of pairs, each
+    (width, height, channels): what each step of the method must move, every
     candidate gather counted, no cache reuse.  The level init runs inside the
     row phase's first pass of iteration 0, so its bytes are charged there."""
-    dims = level_dims(W0, H0, LEVELS)
-    px = [w * h for w, h in dims]
-    p0, pall, pc = px[0], sum(px), px[-1]
-    per_step = {
-        "gray": 4 * p0 * 2 * batch,                               # 3 B RGB in, 1 B luma out, 2 images
-        "down2": sum(5 * q for q in px[1:]) * 2 * batch,          # 4 B in, 1 B out per output pixel
-        "desc": 33 * pall * 2 * batch,                            # 1 B luma in, 2 x 16 B out
-        "seed_records": 80 * pc * 2 * batch,                      # 16 B in, 64 B record out
-        "row_phase": (2 * ROW_BYTES_PER_PX + INIT_BYTES_PER_PX) * pall * 2 * batch,
-        "col_phase": 2 * COL_BYTES_PER_PX * pall * 2 * batch,
-        "fb": 25 * p0 * 2 * batch,                                # own 8 + other 8 in, 4 + 4 + 1 out
-    }
+    tot = {k: 0 for k in ("gray", "down2", "desc", "seed_records", "row_phase", "col_phase", "fb")}
+    for w, h, c in shapes:
+        px = [a * b for a, b in level_dims(w, h, levels)]
+        p0, pall, pc = px[0], sum(px), px[-1]
+        tot["gray"] += (c + 1) * p0 * 2                          # C B in, 1 B luma out, 2 images
+        tot["down2"] += sum(5 * q for q in px[1:]) * 2           # 4 B in, 1 B out per output pixel
+        tot["desc"] += 33 * pall * 2                             # 1 B luma in, 2 x 16 B out
+        tot["seed_records"] += 80 * pc * 2                       # 16 B in, 64 B record out
+        tot["row_phase"] += (iters * ROW_BYTES_PER_PX + INIT_BYTES_PER_PX) * pall * 2
+        tot["col_phase"] += iters * COL_BYTES_PER_PX * pall * 2
+        tot["fb"] += 25 * p0 * 2                                 # own 8 + other 8 in, 4 + 4 + 1 out
+    return tot
+
+
+def rooflines(prof, per_pass, passes):
+    """Each kernel's algorithmic bytes per pass / its device time per pass,
+    against the HBM peak."""
     out = {}
-    for k, b in per_step.items():
+    for k, b in per_pass.items():
         if k not in prof:
             continue
-        sec = prof[k][1] / 1000.0 / steps
+        sec = prof[k][1] / 1000.0 / passes
         gbs = b / sec / 1e9
         out[k] = {"bytes_per_step": b, "us_per_step": sec * 1e6, "achieved": gbs, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
     return out
+
+
+def kernel_rooflines(prof, batch, steps):
+    """Every kernel of the benchmark step (a batch of 1242x375 RGB pairs)
+    against HBM."""
+    return rooflines(prof, step_bytes([(W0, H0, 3)] * batch, LEVELS), steps)
 
 
 def make_inputs(torch, batch, distinct):
@@ -139,13 +150,17 @@ def serve_bench(torch, ff, n_req, lanes, budget):
     from paper_1805_03517_amd import synth
     reqs, pool = synth.config3_requests(seed=3, n=n_req, per_kind=2)
     dev = {k: (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for k, (a, b) in pool.items()}
+    # the served handle's lanes take the whole budget; the plain baseline
+    # runs on a handle of its own under the same budget
     m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
                    hbm_budget=budget)
+    mp = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
+                    hbm_budget=budget)
     outs = [m._outputs(r["size"][1], r["size"][0], True, True) for r in reqs]
     px = sum(r["size"][0] * r["size"][1] for r in reqs)
-    # warm both paths
+    # warm the plain path
     for r, o in list(zip(reqs, outs))[:8]:
-        m.match(*dev[r["pool_key"]], out=o)
+        mp.match(*dev[r["pool_key"]], out=o)
     torch.cuda.synchronize()
     m.serve_config(lanes=lanes, lane_bytes=budget // lanes)
 
@@ -155,7 +170,7 @@ def serve_bench(torch, ff, n_req, lanes, budget):
         for r, o, a in zip(reqs, outs, arr):
             while time.perf_counter() - t0 < a:
                 pass
-            m.match(*dev[r["pool_key"]], out=o)
+            mp.match(*dev[r["pool_key"]], out=o)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t0 - a)
         return lat, time.perf_counter() - t0
@@ -184,13 +199,21 @@ def serve_bench(torch, ff, n_req, lanes, budget):
     lat, span = plain(burst)
     mu = len(reqs) / span
     rate = 0.7 * mu
-    arr = list(np.cumsum([r["unit_gap"] for r in reqs]) / rate)
+    gaps = np.cumsum([r["unit_gap"] for r in reqs])
+    arr = list(gaps / rate)
     out = {"requests": len(reqs), "sizes": [list(s) for s in synth.SERVE_SIZES], "lanes": lanes,
            "hbm_budget": budget, "plain_service_rate": mu, "arrival_rate": rate,
            "burst": {"plain": summary(lat, span)}}
     out["burst"]["served"] = summary(*served(burst))
     out["poisson"] = {"plain": summary(*plain(arr)), "served": summary(*served(arr))}
+    # near saturation: arrivals at 0.9 x the served burst rate (about 3-4 x
+    # what the plain path can serve), served only -- the plain queue would
+    # grow without bound
+    mu_s = out["burst"]["served"]["pairs_per_s"]
+    arr9 = list(gaps / (0.9 * mu_s))
+    out["poisson_near_capacity"] = {"arrival_rate": 0.9 * mu_s, "served": summary(*served(arr9))}
     m.close()
+    mp.close()
     return out
 
 
@@ -331,8 +354,13 @@ def subpix_bench(torch, ff, pairs, steps, sub_iters=1, sub_radius=2):
         n, ms = prof[k]
         avg_s = ms / n / 1000.0
         loads = 4 * cands * W * H * 2 * len(pairs)
+        # algorithmic bytes: 64 B (the 2x2 neighbourhood) per candidate plus
+        # own descriptor and state in and out (32 B) per pixel and direction
+        nbytes = (64 * cands + 32) * W * H * 2 * len(pairs)
         kern[k] = {"avg_us": avg_s * 1e6, "candidates_per_px": cands, "loads_per_launch": loads,
-                   "g_loads_per_s": loads / avg_s / 1e9}
+                   "g_loads_per_s": loads / avg_s / 1e9, "algorithmic_bytes_per_launch": nbytes,
+                   "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": nbytes / avg_s / 1e9 / HBM_PEAK_GBS}
     return {"sub_iters": sub_iters, "sub_radius_quarter_px": sub_radius, "pairs_per_s": len(pairs) * steps / wall,
             "fractional_flow_fraction_fwd": frac_px, "consistent_fraction_fwd": consistent, "kernels": kern}
 
@@ -398,20 +426,34 @@ def c4_bench(torch, ff, n_pairs):
     for _ in range(2):                          # second call captures the graph
         mb.match_batch(dev, outs=ob)
     tuning = mb.autotune(dev, outs=ob)
+    prep = mb.prepare_batch(dev, outs=ob)       # the ff_pair array, marshalled once
     for _ in range(2):
-        mb.match_batch(dev, outs=ob)
+        mb.match_prepared(prep)
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        mb.match_batch(dev, outs=ob)
+        mb.match_prepared(prep)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
-    # seed search of the batch on i8 MFMA: one grouped launch over all pairs
+    # the same with the array rebuilt in Python for every call
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mb.match_batch(dev, outs=ob)
+    torch.cuda.synchronize()
+    tb_marshal = (time.perf_counter() - t0) / reps
+    # per-kernel device time of the batched call (events around every
+    # launch); seed search of the batch on i8 MFMA: one grouped launch
     mb.profile(True)
-    mb.match_batch(dev, outs=ob)
+    for _ in range(reps):
+        mb.match_prepared(prep)
     prof = mb.profile_read()
     mb.profile(False)
+    shapes = [(a.shape[1], a.shape[0], 1) for a, _, _ in pairs]
+    per_call = step_bytes(shapes, 3)
+    total_bytes = sum(per_call.values())
+    kern = {k: {"launches_per_call": v[0] // reps, "us_per_call": 1000.0 * v[1] / reps} for k, v in prof.items()}
+    roof = rooflines(prof, per_call, reps)
     useful = 0
     for a, _, _ in pairs:
         wc, hc = a.shape[1] >> 2, a.shape[0] >> 2              # coarsest of 3 levels
@@ -419,6 +461,7 @@ def c4_bench(torch, ff, n_pairs):
     sn, sms = prof["seed_nn"]
     rn, rms = prof["seed_resolve"]
     seed = {"avg_us": 1000.0 * sms / sn, "resolve_us": 1000.0 * rms / rn,
+            "resolve_share": rms / (rms + sms),
             "useful_tops": useful / (sms / sn * 1e-3) / 1e12}
     seed["issued_tops"] = 4 * seed["useful_tops"]
     seed["useful_frac"] = seed["useful_tops"] / I8_PEAK_TOPS
@@ -434,9 +477,40 @@ def c4_bench(torch, ff, n_pairs):
     same = all(torch.equal(x[k], y[k]) for x, y in zip(ob, op) for k in x)
     mb.close()
     mp.close()
-    return {"pairs": n_pairs, "batched": {"pairs_per_s": n_pairs / tb, "px_per_s": px / tb, "ms": 1000 * tb},
+    kernel_ms = sum(v["us_per_call"] for v in kern.values()) / 1000.0
+    return {"pairs": n_pairs, "batched": {"pairs_per_s": n_pairs / tb, "px_per_s": px / tb, "ms": 1000 * tb,
+                                          "algorithmic_bytes": total_bytes,
+                                          "algorithmic_frac": total_bytes / tb / 1e9 / HBM_PEAK_GBS,
+                                          "kernel_ms": kernel_ms,
+                                          "ms_marshalling_every_call": 1000 * tb_marshal},
             "per_pair": {"pairs_per_s": n_pairs / tp, "px_per_s": px / tp, "ms": 1000 * tp},
-            "bit_identical": bool(same), "schedule": tuning, "seed_nn": seed}
+            "bit_identical": bool(same), "schedule": tuning, "seed_nn": seed, "kernels": kern,
+            "kernel_rooflines": roof}
+
+
+def plain_bench(torch, m, pairs, outs, rounds, batched_ms_per_pair):
+    """The plain path on the benchmark batch: one ff_match_pair call per pair
+    (same handle, schedule and outputs), back to back for throughput, then
+    each call synchronised on its own for its latency."""
+    import numpy as np
+    print("[bench] plain per-pair path", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        for (a, b), o in zip(pairs, outs):
+            m.match(a, b, out=o)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    lat = []
+    for (a, b), o in zip(pairs, outs):
+        t1 = time.perf_counter()
+        m.match(a, b, out=o)
+        torch.cuda.synchronize()
+        lat.append(1000.0 * (time.perf_counter() - t1))
+    n = len(pairs) * rounds
+    return {"calls": n, "pairs_per_s": n / dtp, "px_per_s": n * W0 * H0 / dtp,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "batched_ms_per_pair": batched_ms_per_pair}
 
 
 def main():
@@ -450,7 +524,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="host threads for the all-core oracle run (0: this process's CPUs, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--plain", action="store_true", help="also time per-pair ff_match_pair calls")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-pair ff_match_pair leg")
     ap.add_argument("--autotune", action="store_true", help="re-tune the line-kernel schedule first")
     ap.add_argument("--default-schedule", action="store_true", help="the handle's default schedule")
     ap.add_argument("--seednn-only", action="store_true",
@@ -513,12 +587,14 @@ def main():
     torch.cuda.synchronize()
 
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    prep = m.prepare_batch(pairs, outs=outs)    # the ff_pair array, marshalled once
+    m.match_prepared(prep)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        m.match_batch(pairs, outs=outs)
+        m.match_prepared(prep)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -532,7 +608,7 @@ def main():
     print("[bench] per-kernel timing", file=sys.stderr, flush=True)
     m.profile(True)
     for _ in range(args.steps):
-        m.match_batch(pairs, outs=outs)
+        m.match_prepared(prep)
     prof = m.profile_read()
     m.profile(False)
     dims = level_dims(W0, H0, LEVELS)
@@ -558,16 +634,8 @@ def main():
         seednn = seednn_bench(torch, ff, pairs[0], (sl, sms, args.batch, 1000.0 * rms / rl))
 
     plain = None
-    if args.plain:
-        print("[bench] plain per-pair path", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(max(1, args.steps // 4)):
-            for (a, b), o in zip(pairs, outs):
-                m.match(a, b, out=o)
-        torch.cuda.synchronize()
-        dtp = time.perf_counter() - t0
-        plain = {"pairs_per_s": args.batch * max(1, args.steps // 4) / dtp}
+    if not args.no_plain and not args.core:
+        plain = plain_bench(torch, m, pairs, outs, max(1, args.steps // 4), ms_per_step / args.batch)
 
     sparse = None
     if not args.core:

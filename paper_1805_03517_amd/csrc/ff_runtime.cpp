@@ -53,6 +53,13 @@ void noalloc_unlock(int device);
 
 using namespace ff;
 
+// Launch geometry of one batch: the largest level sizes over its pairs.
+struct Dims {
+    int n = 0;
+    int maxW[kMaxLevels] = {0}, maxH[kMaxLevels] = {0}, maxPx[kMaxLevels] = {0};
+    int maxQ = 0;
+};
+
 struct ff_ctx {
     ff_params prm{};
     int device = 0;
@@ -80,6 +87,13 @@ struct ff_ctx {
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
     std::vector<PairDev> last;       // what d_table holds now
+    // the last call's pair array as the caller passed it, with its launch
+    // geometry: a call with byte-identical pairs on the same arena reuses
+    // the validated plan and the device table as they are
+    std::vector<ff_pair> last_pairs;
+    void* last_arena = nullptr;
+    Dims last_dims;
+    bool last_valid = false;
     // stream ordering between calls: every call records run_done on its
     // stream, and a call on another stream first waits for it, since all
     // calls share the arena and the device table
@@ -251,6 +265,7 @@ ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
         h->arena = nullptr;
         h->arena_bytes = 0;
         h->last.clear();
+        h->last_pairs.clear();
     }
     size_t want = exact ? need : need + need / 8;           // head-room against regrowth
     if (h->prm.hbm_budget) want = std::min<size_t>(want, h->prm.hbm_budget - lanes);
@@ -423,12 +438,6 @@ void prof_end(ff_ctx* h, long i, hipStream_t st)
     } while (0)
 
 // Enqueue the whole search (or, for a debug stop, the part up to it).
-// Launch geometry of one batch: the largest level sizes over its pairs.
-struct Dims {
-    int n = 0;
-    int maxW[kMaxLevels] = {0}, maxH[kMaxLevels] = {0}, maxPx[kMaxLevels] = {0};
-    int maxQ = 0;
-};
 
 // Enqueue the launch sequence on `st`.  With an active stop, enqueue only up
 // to that point and copy the intermediate of pair 0 (tab0 / plan0).
@@ -645,6 +654,24 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
 {
     if (n < 1 || n > 32767) return fail(h, FF_ERR_INVALID, "batch size must be in 1..32767");
     const ff_params& p = h->prm;
+    // the same pair array as the previous call, on the same arena: its
+    // validation, plan and device table still hold (the table was uploaded
+    // by that call and nothing has replaced it since)
+    if (!stop.active && h->last_valid && h->arena && h->arena == h->last_arena && (size_t)n == h->last_pairs.size() &&
+        std::memcmp(pairs, h->last_pairs.data(), (size_t)n * sizeof(ff_pair)) == 0) {
+        FF_HIP(h, hipSetDevice(h->device));
+        if (h->run_any && st != h->run_stream) FF_HIP(h, hipStreamWaitEvent(st, h->run_done, 0));
+        const Dims& D = h->last_dims;
+        ff_status s = (!h->prof_on && h->use_graphs) ? launch_graph(h, h->d_table, D, st)
+                                                    : enqueue(h, h->d_table, D, st, Stop{}, nullptr, nullptr);
+        if (s != FF_OK) return s;
+        FF_HIP(h, hipGetLastError());
+        FF_HIP(h, hipEventRecord(h->run_done, st));
+        h->run_stream = st;
+        h->run_any = true;
+        return FF_OK;
+    }
+    h->last_pairs.clear();
     std::vector<PairPlan> plans(n);
     size_t need = 0;
     for (int i = 0; i < n; ++i) {
@@ -683,6 +710,12 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     FF_HIP(h, hipEventRecord(h->run_done, st));
     h->run_stream = st;
     h->run_any = true;
+    if (!stop.active) {
+        h->last_dims = D;
+        h->last_valid = true;
+        h->last_pairs.assign(pairs, pairs + n);
+        h->last_arena = h->arena;
+    }
     return FF_OK;
 }
 
@@ -955,6 +988,7 @@ ff_status serve_configure(ff_ctx* h, int lanes, size_t lane_bytes)
         h->arena = nullptr;
         h->arena_bytes = 0;
         h->last.clear();
+        h->last_pairs.clear();
     }
     ServeState* sv = new ServeState;
     h->serve = sv;

@@ -62,6 +62,14 @@ class Stage(ctypes.Structure):
                 ("level", ctypes.c_int32), ("iter", ctypes.c_int32), ("step", ctypes.c_int32)]
 
 
+class PreparedBatch:
+    """An ff_pair array built once (Matcher.prepare_batch) and the tensors
+    it points to."""
+
+    def __init__(self, arr, n, pairs, outs):
+        self.arr, self.n, self.pairs, self.outs = arr, n, pairs, outs
+
+
 _lib = None
 
 
@@ -208,12 +216,22 @@ class Matcher:
         self._check(lib().ff_match_pair_noalloc(self._h, ctypes.byref(p), _stream_ptr(self._torch, self.device)))
         return o
 
-    def match_batch(self, pairs, bwd=True, cost=True, outs=None):
+    def prepare_batch(self, pairs, bwd=True, cost=True, outs=None):
+        """Marshal a batch once: the ff_pair array of these inputs and
+        outputs, for repeated ff_match_batch calls (match_prepared) without
+        rebuilding it in Python each time.  Keeps the tensors alive."""
         outs = outs if outs is not None else [
             self._outputs(int(a.shape[0]), int(a.shape[1]), bwd, cost) for a, _ in pairs]
         arr = (Pair * len(pairs))(*[self._pair(a, b, o) for (a, b), o in zip(pairs, outs)])
-        self._check(lib().ff_match_batch(self._h, arr, len(pairs), _stream_ptr(self._torch, self.device)))
-        return outs
+        return PreparedBatch(arr, len(pairs), pairs, outs)
+
+    def match_prepared(self, prep):
+        """ff_match_batch on a prepared batch; returns its outputs."""
+        self._check(lib().ff_match_batch(self._h, prep.arr, prep.n, _stream_ptr(self._torch, self.device)))
+        return prep.outs
+
+    def match_batch(self, pairs, bwd=True, cost=True, outs=None):
+        return self.match_prepared(self.prepare_batch(pairs, bwd, cost, outs))
 
     def workspace_bytes(self, shapes):
         arr = (Pair * len(shapes))(*[Pair(None, None, w, h, c) for (h, w, c) in shapes])

@@ -112,3 +112,53 @@ def test_budget_covers_arena_and_serving_lanes(torch, ffm):
         m.serve_config(lanes=3, lane_bytes=need + 1)   # the lanes alone exceed the budget
     assert e.value.status == ffm.FF_ERR_BUDGET
     m.close()
+
+
+def test_repeated_pair_array_after_other_calls(torch, ffm, orc):
+    """A batch whose ff_pair array is passed again unchanged reuses the
+    validated plan and the device table; calls that replace the table in
+    between (another batch, a single pair, a debug stage, a new schedule)
+    must not leave it stale.  Every repeat equals the first result, and the
+    first equals the oracle."""
+    rng = np.random.default_rng(401)
+    pairs = []
+    for k in range(5):
+        W, H = int(rng.integers(64, 220)), int(rng.integers(64, 180))
+        d = (int(rng.integers(-16, 17)), int(rng.integers(-16, 17)))
+        pairs.append(synth.translated_pair(np.random.default_rng(410 + k), W, H, d=d)[:2])
+    m = ffm.Matcher(levels=3)
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b in pairs]
+    prep = m.prepare_batch(dev)
+    say("repeated pair array: first call")
+    m.match_prepared(prep)
+    torch.cuda.synchronize()
+    first = [{k: v.clone() for k, v in o.items()} for o in prep.outs]
+    p = orc.params(levels=3)
+    for k, (a, b) in enumerate(pairs):
+        _same(orc.match(a, b, p), first[k], f"member {k}")
+
+    def again(tag):
+        say("repeated pair array after", tag)
+        for o in prep.outs:
+            for v in o.values():
+                v.fill_(-1 if v.dtype != torch.uint8 else 255)
+        m.match_prepared(prep)
+        torch.cuda.synchronize()
+        for k, o in enumerate(prep.outs):
+            for key in o:
+                assert torch.equal(o[key], first[k][key]), (tag, k, key)
+
+    again("itself (graph capture)")
+    again("itself (graph replay)")
+    m.match_batch(dev[::-1][:3])
+    again("another batch")
+    m.match(*dev[2])
+    again("a single pair")
+    m.debug_stage(dev[0][0], dev[0][1], ffm.STAGE_STATE, dir=1, level=1, iter=0, step=4)
+    again("a debug stage")
+    m.set_tuning([2, 8, 0] * 3 + [1, 4, 0] * 3)
+    again("a schedule change")
+    big = [(_dev(torch, a), _dev(torch, b)) for a, b in (synth.config1(seed=402)[:2],)]
+    m.match_batch(big)                                   # grows the arena
+    again("an arena regrowth")
+    m.close()
