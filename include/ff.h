@@ -302,6 +302,18 @@ typedef struct {
 ff_status ff_debug_stage(ff_handle h, const ff_pair* pair, const ff_stage* which,
                          void* dst, void* stream);
 
+/* Allocation fault injection, for tests of the error paths (not part of the
+ * method): from now on the first `after` device or pinned allocations the
+ * handle makes (its workspace, pair table, staging buffers and serving
+ * lanes) succeed and every later one fails as the device being out of
+ * memory; after < 0 switches it off.  A call that meets such a failure
+ * returns FF_ERR_OOM and leaves the handle usable; what the handle did
+ * allocate before the failure stays owned by it (reused by later calls,
+ * freed by ff_destroy), so nothing leaks.  The environment variable FF_FAULT_ALLOC_AFTER=n sets
+ * the same from ff_create on (which then returns FF_ERR_OOM when its own
+ * staging allocation fails).  FF_ERR_INVALID for a NULL handle. */
+ff_status ff_debug_fault_alloc(ff_handle h, int64_t after);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,6 +100,12 @@ struct ff_ctx {
     hipEvent_t run_done = nullptr;
     hipStream_t run_stream = nullptr;
     bool run_any = false;
+    // allocation fault injection (tests): with fault_after = n >= 0, the
+    // first n device or pinned allocations made for this handle (its serving
+    // lanes included) succeed and every later one fails as out of memory
+    ff_ctx* fault_root = this;
+    long long fault_after = -1;
+    long long allocs = 0;
     // tracing: event pairs around every launch while enabled
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -248,6 +254,28 @@ ff_status validate_pair(ff_ctx* h, const ff_pair& q)
 // Bytes the handle's serving lanes hold (0 when serving is not configured).
 size_t serve_bytes(const ff_ctx* h);
 
+// Every device or pinned allocation of the runtime goes through these two,
+// which apply the handle's fault injection.
+bool alloc_faulted(ff_ctx* h)
+{
+    ff_ctx* r = h->fault_root;
+    if (r->fault_after >= 0 && r->allocs >= r->fault_after) return true;
+    ++r->allocs;
+    return false;
+}
+
+hipError_t dev_malloc(ff_ctx* h, void** p, size_t bytes)
+{
+    if (alloc_faulted(h)) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(ff_ctx* h, void** p, size_t bytes)
+{
+    if (alloc_faulted(h)) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
 ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
 {
     // one budget per handle: its own arena and its serving lanes together
@@ -269,10 +297,10 @@ ff_status ensure_arena(ff_ctx* h, size_t need, bool exact = false)
     }
     size_t want = exact ? need : need + need / 8;           // head-room against regrowth
     if (h->prm.hbm_budget) want = std::min<size_t>(want, h->prm.hbm_budget - lanes);
-    hipError_t e = hipMalloc(&h->arena, want);
+    hipError_t e = dev_malloc(h, &h->arena, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        e = hipMalloc(&h->arena, need);
+        e = dev_malloc(h, &h->arena, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             h->arena = nullptr;
@@ -360,7 +388,13 @@ ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t s
             h->d_table = nullptr;
         }
         const size_t cap = std::max<size_t>(n, 16);
-        FF_HIP(h, hipMalloc((void**)&h->d_table, cap * sizeof(PairDev)));
+        h->d_table_cap = 0;
+        if (dev_malloc(h, (void**)&h->d_table, cap * sizeof(PairDev)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->d_table = nullptr;
+            h->last.clear();
+            return fail(h, FF_ERR_OOM, "hipMalloc of the device pair table failed");
+        }
         h->d_table_cap = cap;
     }
     const int k = (int)(h->staging_next++ % ff_ctx::kStaging);
@@ -369,7 +403,12 @@ ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t s
         if (h->h_table[k]) FF_HIP(h, hipHostFree(h->h_table[k]));
         h->h_table[k] = nullptr;
         const size_t cap = std::max<size_t>(n, 16);
-        FF_HIP(h, hipHostMalloc((void**)&h->h_table[k], cap * sizeof(PairDev), hipHostMallocDefault));
+        h->h_table_cap[k] = 0;
+        if (pinned_malloc(h, (void**)&h->h_table[k], cap * sizeof(PairDev)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->h_table[k] = nullptr;
+            return fail(h, FF_ERR_OOM, "pinned staging allocation failed");
+        }
         h->h_table_cap[k] = cap;
     }
     std::memcpy(h->h_table[k], tab.data(), n * sizeof(PairDev));
@@ -891,11 +930,21 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
 
 void free_ctx(ff_ctx* h);
 
-ff_ctx* make_ctx(const ff_params& p, int device)
+// A handle on `device`; `root` (or the new handle itself) holds the
+// allocation fault injection, which starts from FF_FAULT_ALLOC_AFTER when
+// that is set.  On failure returns null and *st names why (FF_ERR_OOM when a
+// pinned allocation failed), having released everything it made.
+ff_ctx* make_ctx(const ff_params& p, int device, ff_ctx* root, ff_status* st)
 {
+    *st = FF_ERR_HIP;
     ff_ctx* h = new ff_ctx;
     h->prm = p;
     h->device = device;
+    if (root) {
+        h->fault_root = root;
+    } else if (const char* f = std::getenv("FF_FAULT_ALLOC_AFTER")) {
+        h->fault_after = std::atoll(f);
+    }
     if (hipSetDevice(device) != hipSuccess) {
         delete h;
         return nullptr;
@@ -909,17 +958,23 @@ ff_ctx* make_ctx(const ff_params& p, int device)
     }
     // the staging ring starts with room for 16 pairs per slot, so a
     // single-pair call never allocates pinned memory
-    bool ok = hipEventCreateWithFlags(&h->run_done, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; ok && k < ff_ctx::kStaging; ++k) {
-        ok = hipHostMalloc((void**)&h->h_table[k], 16 * sizeof(PairDev), hipHostMallocDefault) == hipSuccess;
-        if (ok) h->h_table_cap[k] = 16;
-    }
-    if (!ok) {
+    if (hipEventCreateWithFlags(&h->run_done, hipEventDisableTiming) != hipSuccess) {
         free_ctx(h);
         return nullptr;
     }
+    for (int k = 0; k < ff_ctx::kStaging; ++k) {
+        if (pinned_malloc(h, (void**)&h->h_table[k], 16 * sizeof(PairDev)) != hipSuccess) {
+            (void)hipGetLastError();
+            h->h_table[k] = nullptr;
+            free_ctx(h);
+            *st = FF_ERR_OOM;
+            return nullptr;
+        }
+        h->h_table_cap[k] = 16;
+    }
     const char* g = std::getenv("FF_GRAPHS");
     h->use_graphs = !(g && g[0] == '0');
+    *st = FF_OK;
     return h;
 }
 
@@ -998,10 +1053,11 @@ ff_status serve_configure(ff_ctx* h, int lanes, size_t lane_bytes)
     ff_params sub = h->prm;
     sub.hbm_budget = 0;                       // the parent handle enforces the budget
     for (ServeLane& l : sv->lanes) {
-        l.exec = make_ctx(sub, h->device);
+        ff_status cs = FF_OK;
+        l.exec = make_ctx(sub, h->device, h->fault_root, &cs);
         if (!l.exec) {
             free_serve(h);
-            return fail(h, FF_ERR_HIP, "lane context creation failed");
+            return fail(h, cs, "lane context creation failed");
         }
         if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess) {
@@ -1076,8 +1132,9 @@ ff_status ff_create(const ff_params* params, int device, ff_handle* out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FF_ERR_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FF_ERR_UNSUPPORTED;
-    ff_ctx* h = make_ctx(*params, device);
-    if (!h) return FF_ERR_HIP;
+    ff_status cs = FF_OK;
+    ff_ctx* h = make_ctx(*params, device, nullptr, &cs);
+    if (!h) return cs;
     // the allocation-free entry point's scratch on this device (once per
     // device; a failure here surfaces only on that entry point)
     (void)noalloc_setup(device);
@@ -1123,6 +1180,15 @@ ff_status ff_debug_stage(ff_handle h, const ff_pair* pair, const ff_stage* which
     s.st = w;
     s.dst = dst;
     return run(h, pair, 1, (hipStream_t)stream, s);
+}
+
+ff_status ff_debug_fault_alloc(ff_handle h, int64_t after)
+{
+    if (!h) return FF_ERR_INVALID;
+    if (h->fault_root != h) return fail(h, FF_ERR_INVALID, "not a root handle");
+    h->fault_after = after < 0 ? -1 : after;
+    h->allocs = 0;
+    return FF_OK;
 }
 
 uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n)

@@ -25,7 +25,7 @@ INF = 2**31 - 1
 EXPORTS = ("ff_create", "ff_match_pair", "ff_match_batch", "ff_match_pair_noalloc", "ff_destroy", "ff_last_error",
            "ff_workspace_bytes", "ff_serve_config", "ff_submit", "ff_poll", "ff_serve_inflight",
            "ff_autotune", "ff_tune_get", "ff_tune_set", "ff_profile_enable", "ff_profile_read",
-           "ff_debug_stage")
+           "ff_debug_stage", "ff_debug_fault_alloc")
 
 
 class FFError(RuntimeError):
@@ -116,6 +116,8 @@ def lib():
         l.ff_profile_read.restype = i32
         l.ff_debug_stage.argtypes = [vp, ctypes.POINTER(Pair), ctypes.POINTER(Stage), vp, vp]
         l.ff_debug_stage.restype = ctypes.c_int
+        l.ff_debug_fault_alloc.argtypes = [vp, ctypes.c_int64]
+        l.ff_debug_fault_alloc.restype = ctypes.c_int
         _lib = l
     return _lib
 
@@ -270,6 +272,11 @@ class Matcher:
                                          ctypes.c_void_p(dst.data_ptr()),
                                          _stream_ptr(self._torch, self.device)))
         return dst
+
+    def fault_alloc(self, after):
+        """ff_debug_fault_alloc: the first `after` allocations from now on
+        succeed, later ones fail as out of memory (after < 0: off)."""
+        self._check(lib().ff_debug_fault_alloc(self._h, int(after)))
 
     # -- serving ----------------------------------------------------------
     def serve_config(self, lanes=4, lane_bytes=4 << 30):

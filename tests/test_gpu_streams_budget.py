@@ -162,3 +162,68 @@ def test_repeated_pair_array_after_other_calls(torch, ffm, orc):
     m.match_batch(big)                                   # grows the arena
     again("an arena regrowth")
     m.close()
+
+
+def test_allocation_faults_return_oom_without_leaks(torch, ffm, orc, monkeypatch):
+    """Injected allocation failures (ff_debug_fault_alloc, and
+    FF_FAULT_ALLOC_AFTER at creation) give FF_ERR_OOM at every allocation
+    site -- handle creation, workspace arena, pair table, serving lanes --
+    the handle stays usable and bit-exact afterwards, and once every handle
+    is destroyed the device's free memory is back where it started."""
+    i1, i2, _ = synth.config0()
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    ref = ffm.Matcher(levels=3)
+    out = ref._outputs(96, 128)
+    want = {k: v.clone() for k, v in ref.match(a, b, out=out).items()}
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    say("fault injection at creation (four pinned staging buffers)")
+    for k in range(4):
+        monkeypatch.setenv("FF_FAULT_ALLOC_AFTER", str(k))
+        with pytest.raises(ffm.FFError) as e:
+            ffm.Matcher(levels=3)
+        assert e.value.status == ffm.FF_ERR_OOM, k
+    monkeypatch.delenv("FF_FAULT_ALLOC_AFTER")
+    say("fault injection in a call (arena, then pair table)")
+    for k in range(2):
+        m = ffm.Matcher(levels=3)
+        m.fault_alloc(k)
+        with pytest.raises(ffm.FFError) as e:
+            m.match(a, b, out=out)
+        assert e.value.status == ffm.FF_ERR_OOM, k
+        m.fault_alloc(-1)
+        got = m.match(a, b, out=out)
+        torch.cuda.synchronize()
+        for key in want:
+            assert torch.equal(got[key], want[key]), (k, key)
+        m.close()
+    m = ffm.Matcher(levels=3)
+    m.fault_alloc(2)
+    m.match(a, b, out=out)                                # arena + table: exactly two
+    torch.cuda.synchronize()
+    m.close()
+    say("fault injection while configuring two serving lanes")
+    need = ref.workspace_bytes([(96, 128, 1)])
+    for k in (0, 3, 4, 7, 9):
+        m = ffm.Matcher(levels=3)
+        m.fault_alloc(k)
+        with pytest.raises(ffm.FFError) as e:
+            m.serve_config(lanes=2, lane_bytes=need)
+        assert e.value.status == ffm.FF_ERR_OOM, k
+        assert m.inflight() == 0
+        m.fault_alloc(-1)
+        m.serve_config(lanes=2, lane_bytes=need)
+        o = m.submit(a, b, tag=k)
+        import time
+        t0, got = time.time(), []
+        while not got and time.time() - t0 < 60:
+            got = m.poll()
+        assert got == [k]
+        for key in want:
+            assert torch.equal(o[key], want[key]), (k, key)
+        m.close()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("free device bytes before / after", free0, free1)
+    assert abs(free0 - free1) < (2 << 20), (free0, free1)
+    ref.close()

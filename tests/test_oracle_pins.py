@@ -1024,3 +1024,73 @@ def test_cost_is_elementwise_sad(orc):
         assert orc.cost(DA, DB, x, y, fx, fy) == ref
     single = abs(int(DA[1, 3, 7]) - int(DB[2, 5, 7]))
     assert orc.cost(DA, DB, 3, 1, 2, 1) == single and single >= 128
+
+
+# ------------------------------------------------------- sanitizers --
+_SAN_CASES = {
+    "wh": dict(levels=3),
+    "census_two_checks": dict(levels=3, cost_kind=1, two_checks=1, seed2=0xBEEF, fb_eps=3),
+    "subpixel": dict(levels=3, sub_iters=2, sub_radius=3),
+    "ragged_stride1_rgb": dict(levels=2, seed_stride=1, rs_radius=5, fb_eps=2),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_SAN_CASES))
+def test_oracle_runs_clean_under_asan_and_ubsan(orc, tmp_path, case):
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report aborts, leaks included) runs the whole search of config 0
+    (and a ragged RGB pair) without a report and gives the outputs of the
+    ordinary build, bit for bit."""
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    exe = tmp_path / "oracle_san"
+    odir = os.path.join(os.path.dirname(HERE), "oracle")
+    subprocess.check_call(["gcc", "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-I" + odir,
+                           os.path.join(odir, "ff_oracle.c"), os.path.join(HERE, "helpers", "oracle_sanitize_main.c"),
+                           "-o", str(exe)])
+    kw = dict(_SAN_CASES[case])
+    if case.startswith("ragged"):
+        rng = np.random.default_rng(51)
+        i1 = rng.integers(0, 256, size=(37, 53, 3), dtype=np.uint8)
+        i2 = np.roll(i1, (2, -3), axis=(0, 1))
+    else:
+        i1, i2, _ = synth.config0()
+    H, W = i1.shape[:2]
+    C = 1 if i1.ndim == 2 else i1.shape[2]
+    prm = orc.params(**kw)
+    hdr = np.array([W, H, C, prm.levels, prm.seed_stride, prm.iters, prm.rs_radius, prm.fb_eps, prm.cost_kind,
+                    prm.two_checks, prm.sub_iters, prm.sub_radius, 4], np.int32)
+    src = tmp_path / "in.bin"
+    with open(src, "wb") as f:
+        f.write(hdr.tobytes())
+        f.write(np.array([prm.seed, prm.seed2], np.uint64).tobytes())
+        f.write(np.ascontiguousarray(i1).tobytes())
+        f.write(np.ascontiguousarray(i2).tobytes())
+    dst = tmp_path / "out.bin"
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([str(exe), str(src), str(dst)], capture_output=True, text=True, env=env, timeout=600)
+    assert res.returncode == 0, res.stderr[-3000:]
+    assert "runtime error" not in res.stderr and "Sanitizer" not in res.stderr, res.stderr[-3000:]
+    raw = open(dst, "rb").read()
+    n = W * H
+    off = 0
+
+    def take(dtype, count, shape):
+        nonlocal off
+        a = np.frombuffer(raw, dtype=dtype, count=count, offset=off).reshape(shape)
+        off += a.nbytes
+        return a
+
+    got = {"flow_f": take(np.int16, 2 * n, (H, W, 2)), "cost_f": take(np.int32, n, (H, W)),
+           "mask_f": take(np.uint8, n, (H, W)), "flow_b": take(np.int16, 2 * n, (H, W, 2)),
+           "cost_b": take(np.int32, n, (H, W)), "mask_b": take(np.uint8, n, (H, W))}
+    err, keep = take(np.int32, n, (H, W)), take(np.uint8, n, (H, W))
+    ref = orc.match(i1, i2, prm)
+    for k in got:
+        assert np.array_equal(got[k], ref[k]), k
+    unit = 4 if prm.sub_iters > 0 else 1
+    e = orc.fb_error(ref["flow_f"], ref["cost_f"], ref["flow_b"], ref["cost_b"], unit=unit)
+    assert np.array_equal(err, e)
+    assert np.array_equal(keep, orc.sparsify(ref["mask_f"], e, 4))
