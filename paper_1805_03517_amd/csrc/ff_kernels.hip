@@ -10,7 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "ff_internal.h"
 
@@ -631,13 +633,18 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
 // A block of 4 waves holds 4 x 16*MQ seeds as MFMA A operands and streams
 // one split of the database: chunks of kSeedChunk tiles are copied once per
 // block into LDS (direct global -> LDS loads) and read by all four waves, so
-// the database crosses L2 once per block instead of once per wave.  Per lane
-// and seed row a wave keeps each chunk's largest score (one v_max3 per two
-// scores) and folds it into max((score << 11) | (2047 - chunk)), so equal
-// scores prefer the earlier chunk; splits merge (score, chunk) per seed and
-// k_seed_resolve picks the lowest index inside the winning chunk -- the
-// lowest index wins every tie.
-// grid (ceil(seed tiles / 4), splits, 2 * pairs), 256 threads.
+// the database crosses L2 once per block instead of once per wave.  Each
+// tile sits in LDS in lane order -- slot 16 g + n holds group g of record n,
+// the 16 bytes lane n + 16 g feeds to the MFMA -- so a wave reads a tile as
+// 64 consecutive 16-byte slots, free of bank conflicts (the copy permutes
+// its source addresses inside the tile's kilobyte instead).  A wave scores
+// only its seed tiles that hold seeds: a wave, or the tail of one, past the
+// last seed issues no MFMA.  Per lane and seed row a wave keeps each chunk's
+// largest score (one v_max3 per two scores) and folds it into
+// max((score << 11) | (2047 - chunk)), so equal scores prefer the earlier
+// chunk; splits merge (score, chunk) per seed and k_seed_resolve picks the
+// lowest index inside the winning chunk -- the lowest index wins every tie.
+// grid (ceil(seed tiles / (4 MQ)), splits, 2 * pairs), 256 threads.
 constexpr int kSeedChunk = 16;                                   // tiles (16 KiB) per LDS chunk
 constexpr int kNoScore = -(1 << 20);                             // below every score; << 11 gives INT32_MIN
 
@@ -645,17 +652,22 @@ template <int MQ>
 __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pairs, int level,
                                                 int stride, int tiles_per_split)
 {
-    const PairDev& P = pairs[blockIdx.z >> 1];
-    const int dir = blockIdx.z & 1;
+    // XCD-aware order: the seed blocks streaming one split (consecutive x)
+    // run on one XCD and share the split through its L2
+    const int3 bk = xcd_block3();
+    const PairDev& P = pairs[bk.z >> 1];
+    const int dir = bk.z & 1;
     const LevelDev& L = P.lv[level];
     const int N = L.W * L.H, Q = P.nsx * P.nsy;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (blockIdx.x * 4 * 16 * MQ >= Q) return;                   // no seeds in this block: uniform
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (bk.x * 4 * 16 * MQ >= Q) return;                         // no seeds in this block: uniform
     const int ntiles = (N + 15) >> 4;
-    const int t0 = blockIdx.y * tiles_per_split;
+    const int t0 = bk.y * tiles_per_split;
     if (t0 >= ntiles) return;                                    // uniform
     const int t1 = min(t0 + tiles_per_split, ntiles);
-    const int qbase = (blockIdx.x * 4 + wave) * 16 * MQ;         // may exceed Q: the wave still loads
+    const int qbase = (bk.x * 4 + wave) * 16 * MQ;               // may exceed Q: the wave still copies
+    const int live = min(MQ, max(0, (Q - qbase + 15) >> 4));    // seed tiles of this wave holding seeds
     const int m = lane & 15, g = lane >> 4;
     __shared__ v4i tiles[kSeedChunk * 64];
 
@@ -683,60 +695,72 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     const FF_GLOBAL v4i* rec = (const FF_GLOBAL v4i*)P.dbrec[dir ^ 1];
     const v4i zero = v4i{0, 0, 0, 0};
     const uint32_t nrec4 = (uint32_t)N * 4u;                     // valid 16-byte groups of the database
-    const uint32_t lane_off = (uint32_t)(m * 4 + g);
-    for (int tb = t0; tb < t1; tb += kSeedChunk) {
+    // LDS slot e of a chunk holds the chunk's 16-byte group src(e): tile
+    // e / 64, record e % 16, group (e / 16) % 4
+    const uint32_t esrc = (uint32_t)(threadIdx.x & ~63u) | ((threadIdx.x & 15u) << 2) | ((threadIdx.x >> 4) & 3u);
+    for (int tb = t0, c = 0; tb < t1; tb += kSeedChunk, ++c) {
         const int nt = min(kSeedChunk, t1 - tb);
-        // copy tiles tb .. tb+nt-1 (16 records x 64 B each) into LDS; thread e
-        // of the block copies 16-byte groups e, e + 256, ...; a wave's 64 lanes
-        // land on 64 consecutive LDS slots
-        for (int e = threadIdx.x; e < nt * 64; e += 256) {
-            const uint32_t gidx = (uint32_t)tb * 64u + (uint32_t)e;
+        // copy tiles tb .. tb+nt-1 into LDS: thread e fills slots e, e + 256,
+        // ...; a wave's 64 lanes land on 64 consecutive LDS slots
+        for (int e = threadIdx.x, k = 0; e < nt * 64; e += 256, k += 256) {
+            const uint32_t gidx = (uint32_t)tb * 64u + esrc + (uint32_t)k;
             if (gidx < nrec4)
                 __builtin_amdgcn_global_load_lds((const FF_GLOBAL void*)(rec + gidx),
                                                  (__attribute__((address_space(3))) void*)&tiles[e - lane], 16, 0, 0);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        const v4i* __restrict__ T = tiles;
         // the chunk's largest score per lane and seed row: one v_max3 per two
-        // scores, full tiles two at a time
-        const int tfull = min(tb + nt, N >> 4);
-        int cm[MQ][4];
+        // scores, full tiles two at a time; instantiated per number of live
+        // seed tiles so the MFMA chain has no branches
+        auto score = [&](auto LIVE) {
+            constexpr int LV = decltype(LIVE)::value;
+            const int tfull = min(tb + nt, N >> 4);
+            int cm[LV][4];
 #pragma unroll
-        for (int mq = 0; mq < MQ; ++mq)
+            for (int mq = 0; mq < LV; ++mq)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) cm[mq][i] = kNoScore;
-        int t = tb;
-        for (; t + 1 < tfull; t += 2) {
-            const v4i B0 = tiles[(uint32_t)(t - tb) * 64u + lane_off];
-            const v4i B1 = tiles[(uint32_t)(t - tb) * 64u + 64u + lane_off];
+                for (int i = 0; i < 4; ++i) cm[mq][i] = kNoScore;
+            int t = tb;
+            for (; t + 1 < tfull; t += 2) {
+                const v4i B0 = T[(uint32_t)(t - tb) * 64u + (uint32_t)lane];
+                const v4i B1 = T[(uint32_t)(t - tb) * 64u + 64u + (uint32_t)lane];
 #pragma unroll
-            for (int mq = 0; mq < MQ; ++mq) {
-                const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
-                const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
+                for (int mq = 0; mq < LV; ++mq) {
+                    const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
+                    const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], max(acc0[i], acc1[i]));
+                    for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], max(acc0[i], acc1[i]));
+                }
             }
-        }
-        // remaining tile of the chunk, possibly the ragged last one of the plane
-        for (; t < tb + nt; ++t) {
-            const bool nvalid = t * 16 + m < N;
-            const v4i B = tiles[(uint32_t)(t - tb) * 64u + lane_off];
+            // remaining tile of the chunk, possibly the ragged last one of the plane
+            for (; t < tb + nt; ++t) {
+                const bool nvalid = t * 16 + m < N;
+                const v4i B = T[(uint32_t)(t - tb) * 64u + (uint32_t)lane];
 #pragma unroll
-            for (int mq = 0; mq < MQ; ++mq) {
-                const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
+                for (int mq = 0; mq < LV; ++mq) {
+                    const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B, zero, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], nvalid ? acc[i] : kNoScore);
+                    for (int i = 0; i < 4; ++i) cm[mq][i] = max(cm[mq][i], nvalid ? acc[i] : kNoScore);
+                }
             }
-        }
-        // key = (score << 11) | (2047 - chunk): equal scores prefer the earlier chunk
-        const uint32_t tag = (uint32_t)(2047 - (tb - t0) / kSeedChunk);
+            // key = (score << 11) | (2047 - chunk): equal scores prefer the earlier chunk
+            const uint32_t tag = (uint32_t)(2047 - c);
 #pragma unroll
-        for (int mq = 0; mq < MQ; ++mq)
+            for (int mq = 0; mq < LV; ++mq)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) best[mq][i] = max(best[mq][i], (int)(((uint32_t)cm[mq][i] << 11) | tag));
+                for (int i = 0; i < 4; ++i)
+                    best[mq][i] = max(best[mq][i], (int)(((uint32_t)cm[mq][i] << 11) | tag));
+        };
+        static_assert(MQ == 4, "the live-count dispatch below covers MQ = 4");
+        if (live == 4) score(std::integral_constant<int, 4>{});
+        else if (live == 3) score(std::integral_constant<int, 3>{});
+        else if (live == 2) score(std::integral_constant<int, 2>{});
+        else if (live == 1) score(std::integral_constant<int, 1>{});
         __syncthreads();                                         // chunk consumed before it is overwritten
     }
-    if (qbase >= Q) return;
+    if (live == 0) return;
     // Per seed: the best key over its 16 columns; splits merge (score, first
     // tile of the chunk) with a 64-bit atomicMax on (score + 2^20) << 32 |
     // low word, so the merged key names the earliest chunk reaching the best
@@ -745,7 +769,8 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     // with more than 65536 tiles, ~tile and every column.  k_seed_resolve then
     // finds the lowest index inside that chunk.
 #pragma unroll
-    for (int mq = 0; mq < MQ; ++mq)
+    for (int mq = 0; mq < MQ; ++mq) {
+        if (mq >= live) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             int k = best[mq][i];
@@ -761,6 +786,7 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
                 atomicMax(&P.keys[dir][q], key);
             }
         }
+    }
 }
 
 // The lowest database index reaching each seed's best score: the merged key
@@ -1637,21 +1663,35 @@ void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipS
 {
     hipLaunchKernelGGL(k_seed_records, dim3((maxN + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
 }
+// Database splits: few, so that each block streams a long split and pays its
+// prologue, first chunk and epilogue rarely, yet enough to fill the GPU's
+// block slots (four 256-thread blocks per CU at the kernel's register
+// count) in whole rounds: among 1x..4x the smallest count that fills the
+// slots once, the one wasting the fewest slots in its last round (the
+// smaller on ties); whole chunks per split and at most 2048 chunks per split
+// (the chunk tag's range).
 void launch_seed_nn(const PairDev* d, int npairs, int level, int stride, int maxQ, int maxN, hipStream_t st)
 {
     constexpr int MQ = 4;
-    const int qwaves = (maxQ + 16 * MQ - 1) / (16 * MQ);
-    const int ntiles = (maxN + 15) / 16;
-    int tps = 128;
-    int splits = (ntiles + tps - 1) / tps;
-    if (splits > 1024) {
-        splits = 1024;
-        tps = (ntiles + splits - 1) / splits;
+    constexpr long long kSlots = 256 * 5;
+    const int qblocks = (maxQ + 4 * 16 * MQ - 1) / (4 * 16 * MQ);
+    const int nchunks = (maxN + 16 * kSeedChunk - 1) / (16 * kSeedChunk);
+    const long long per_split = (long long)qblocks * 2 * npairs;
+    const long long s0 = std::max<long long>({1, (kSlots + per_split - 1) / per_split, (nchunks + 2047) / 2048});
+    long long splits = std::min<long long>(s0, nchunks);
+    double best_eff = -1.0;
+    for (long long s = s0; s <= 4 * s0 && s <= nchunks; ++s) {
+        const long long blocks = s * per_split, rounds = (blocks + kSlots - 1) / kSlots;
+        const double eff = (double)blocks / (double)(rounds * kSlots);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            splits = s;
+        }
     }
-    if (tps > 2048) tps = 2048;
-    splits = (ntiles + tps - 1) / tps;
-    hipLaunchKernelGGL(k_seed_nn<MQ>, dim3((qwaves + 3) / 4, splits, 2 * npairs), dim3(256), 0, st, d, level,
-                       stride, tps);
+    const int cps = (int)((nchunks + splits - 1) / splits);      // chunks per split
+    const int tps = cps * kSeedChunk;
+    const int nsplit = ((maxN + 15) / 16 + tps - 1) / tps;
+    hipLaunchKernelGGL(k_seed_nn<MQ>, dim3(qblocks, nsplit, 2 * npairs), dim3(256), 0, st, d, level, stride, tps);
 }
 void launch_init(const PairDev* d, int npairs, int level, int coarsest, int stride, int census, int maxpx,
                  hipStream_t st)
