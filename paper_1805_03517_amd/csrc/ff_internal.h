@@ -66,6 +66,13 @@ struct PairDev {
     int2* save[2];                   // first search's level-0 state (second consistency check)
 };
 
+// A line phase's work list over a batch (device memory; see k_line_phase):
+// n items pair-direction << 16 | line block, or items null.
+struct LineWork {
+    const uint32_t* items;
+    int n;
+};
+
 struct SearchConst {
     int levels;
     int stride;

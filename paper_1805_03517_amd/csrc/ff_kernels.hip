@@ -1117,14 +1117,29 @@ struct StageDims {
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
-                                                         int iter, int upto, SearchConst sc, int xw, int finit)
+                                                         int iter, int upto, SearchConst sc, int xw, int finit,
+                                                         const uint32_t* __restrict__ items)
 {
     static_assert(!STG || CK == 0, "the staged random search holds descriptors");
     const uint32_t rlev = sc.rng_level >= 0 ? (uint32_t)sc.rng_level : (uint32_t)level;   // Philox level word
     using FT = typename Feat<CK>::T;
     constexpr size_t FB = CK == 1 ? 8 : 16;                      // feature bytes per pixel
-    const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-    const int pd = lb / gridDim.x, bx = lb % gridDim.x;
+    // The block's pair-direction and line block: from the batch's work list
+    // (items: pair-direction << 16 | line block, every block of every pair
+    // and nothing past a pair's own size; a 1-D grid) or, for a single pair
+    // or pairs of one size, from the 2-D grid (line blocks x pair-directions).
+    // Either way in XCD-aware order, so the lines of one pair-direction
+    // (which gather from the same descriptor plane) share one L2.
+    int pd, bx;
+    if (items) {
+        const uint32_t it = items[xcd_remap(blockIdx.x, gridDim.x)];
+        pd = (int)(it >> 16);
+        bx = (int)(it & 0xFFFFu);
+    } else {
+        const int lb = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+        pd = lb / gridDim.x;
+        bx = lb % gridDim.x;
+    }
     const PairDev& P = pairs[pd >> 1];
     const int dir = pd & 1;
     const LevelDev& L = P.lv[level];
@@ -1723,21 +1738,22 @@ int row_lds_pixels(int maxlen)
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
-                   int maxlen, int finit, hipStream_t st)
+                   int maxlen, int finit, const LineWork& wk, hipStream_t st)
 {
     const int xw = !line_cross_write(WPB, maxlen) ? 0 : COL ? maxlen : row_lds_pixels<CH, WPB>(maxlen);
     const size_t dyn = (size_t)WPB * xw * kLdsBytesPerPx;
-    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), dim3((nlines + WPB - 1) / WPB, 2 * npairs),
-                       dim3(64 * WPB), dyn, st, d, level, iter, upto, sc, xw, finit);
+    const dim3 grid = wk.items ? dim3((unsigned)wk.n) : dim3((nlines + WPB - 1) / WPB, 2 * npairs);
+    hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), grid, dim3(64 * WPB), dyn, st, d, level, iter, upto,
+                       sc, xw, finit, wk.items);
 }
 
 template <int RC, bool COL, int CK>
 bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
-                    const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
+                    const SearchConst& sc, int nlines, int maxlen, int finit, const LineWork& wk, hipStream_t st)
 {
 #define FF_LINE_CASE(C, B, G)                                                                        \
     if (ch == C && wpb == B && stg == G) {                                                           \
-        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st); \
+        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, st); \
         return true;                                                                                 \
     }
     if constexpr (CK == 2) {                                     // the refinement's fixed schedule
@@ -1757,26 +1773,31 @@ bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int 
 
 template <int CK>
 bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter,
-                    int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
+                    int upto, const SearchConst& sc, int nlines, int maxlen, int finit, const LineWork& wk,
+                    hipStream_t st)
 {
     if constexpr (CK == 2) {
         // the refinement: radius 2 (two trials) unrolled, so both trials'
         // neighbourhood loads are in flight together; other radii in a loop
         if (sc.radius == 2)
-            return col ? launch_line_rc<2, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+            return col ? launch_line_rc<2, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0,
+                                                     wk, st)
                        : launch_line_rc<2, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
-                                                      finit, st);
-        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
+                                                      finit, wk, st);
+        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, wk,
+                                                 st)
                    : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit,
-                                                  st);
+                                                  wk, st);
     } else {
         if (sc.radius == 16)
             return col ? launch_line_rc<16, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0,
-                                                      st)
+                                                      wk, st)
                        : launch_line_rc<16, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen,
-                                                       finit, st);
-        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st)
-                   : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, st);
+                                                       finit, wk, st);
+        return col ? launch_line_rc<0, true, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, wk,
+                                                 st)
+                   : launch_line_rc<0, false, CK>(ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, 0, wk,
+                                                  st);
     }
 }
 
@@ -1795,13 +1816,17 @@ bool launch_line_ck(bool col, int ch, int wpb, int stg, const PairDev* d, int np
 // first pass loads each pixel's init flow and costs it instead of reading a
 // state written by k_init); only the software-pipelined pass supports it --
 // see line_fused_init().
+// wk: the batch's work list for this phase and level (items null: the 2-D
+// grid over the batch's largest line count).
 bool launch_line_phase(bool col, int ch, int wpb, int stg, int ck, const PairDev* d, int npairs, int level,
-                       int iter, int upto, const SearchConst& sc, int nlines, int maxlen, int finit, hipStream_t st)
+                       int iter, int upto, const SearchConst& sc, int nlines, int maxlen, int finit,
+                       const LineWork& wk, hipStream_t st)
 {
     if (ck == 2)
-        return stg == 0 && launch_line_ck<2>(col, ch, wpb, 0, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
-    return ck ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st)
-              : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, st);
+        return stg == 0 &&
+               launch_line_ck<2>(col, ch, wpb, 0, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, st);
+    return ck ? launch_line_ck<1>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, st)
+              : launch_line_ck<0>(col, ch, wpb, stg, d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, st);
 }
 
 // Whether the row phase with this schedule can take over the level init.

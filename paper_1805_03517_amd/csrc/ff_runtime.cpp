@@ -33,7 +33,7 @@ void launch_seed_resolve(const PairDev*, int, int, int, int, hipStream_t);
 void launch_init(const PairDev*, int, int, int, int, int, int, hipStream_t);
 void launch_census(const PairDev*, int, int, int, int, hipStream_t);
 bool launch_line_phase(bool, int, int, int, int, const PairDev*, int, int, int, int, const SearchConst&, int, int,
-                       int, hipStream_t);
+                       int, const LineWork&, hipStream_t);
 bool line_fused_init(int ch, int stg, const SearchConst& sc);
 bool line_cross_write(int wpb, int maxlen);
 void launch_transpose_state(const PairDev*, int, int, int, int, int, hipStream_t);
@@ -58,6 +58,11 @@ struct Dims {
     int n = 0;
     int maxW[kMaxLevels] = {0}, maxH[kMaxLevels] = {0}, maxPx[kMaxLevels] = {0};
     int maxQ = 0;
+    // the line phases' work lists (phase 0 rows, 1 columns) for a batch of
+    // uneven pairs: nitems blocks, at byte offset item_off in the device
+    // table; nitems 0 = the 2-D grid over the largest pair
+    int nitems[2][kMaxLevels] = {{0}};
+    size_t item_off[2][kMaxLevels] = {{0}};
 };
 
 struct ff_ctx {
@@ -66,14 +71,14 @@ struct ff_ctx {
     std::string err;
     void* arena = nullptr;
     size_t arena_bytes = 0;
-    PairDev* d_table = nullptr;      // device copy of the per-pair table
-    size_t d_table_cap = 0;          // entries
+    PairDev* d_table = nullptr;      // device copy of the per-pair table (and the work lists after it)
+    size_t d_table_cap = 0;          // bytes
     // pinned staging ring for table uploads: the host refills slot k only
     // after the copy that last read it has finished, so it can run several
     // calls ahead of the device
     static constexpr int kStaging = 4;
-    PairDev* h_table[kStaging] = {};
-    size_t h_table_cap[kStaging] = {};
+    char* h_table[kStaging] = {};
+    size_t h_table_cap[kStaging] = {};   // bytes
     hipEvent_t table_ev[kStaging] = {};
     unsigned staging_next = 0;
     // captured launch sequences, keyed by the batch's launch geometry
@@ -86,7 +91,7 @@ struct ff_ctx {
     std::vector<std::vector<long long>> seen;   // geometries launched once, not yet captured
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
-    std::vector<PairDev> last;       // what d_table holds now
+    std::vector<char> last;          // what d_table holds now
     // the last call's pair array as the caller passed it, with its launch
     // geometry: a call with byte-identical pairs on the same arena reuses
     // the validated plan and the device table as they are
@@ -94,6 +99,8 @@ struct ff_ctx {
     void* last_arena = nullptr;
     Dims last_dims;
     bool last_valid = false;
+    unsigned last_tune_gen = 0;
+    unsigned tune_gen = 0;           // bumped whenever the schedule changes (the work lists depend on it)
     // stream ordering between calls: every call records run_done on its
     // stream, and a call on another stream first waits for it, since all
     // calls share the arena and the device table
@@ -376,10 +383,10 @@ void build_table(const ff_params& p, char* base, const ff_pair* pairs, int n, Pa
     }
 }
 
-ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t st)
+ff_status upload_table(ff_ctx* h, const std::vector<char>& tab, hipStream_t st)
 {
-    const size_t n = tab.size();
-    if (h->last.size() == n && std::memcmp(h->last.data(), tab.data(), n * sizeof(PairDev)) == 0)
+    const size_t n = tab.size();                       // bytes
+    if (h->last.size() == n && std::memcmp(h->last.data(), tab.data(), n) == 0)
         return FF_OK;                                  // device table already current
     if (n > h->d_table_cap) {
         if (h->d_table) {
@@ -387,9 +394,9 @@ ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t s
             FF_HIP(h, hipFree(h->d_table));
             h->d_table = nullptr;
         }
-        const size_t cap = std::max<size_t>(n, 16);
+        const size_t cap = std::max<size_t>(n, 16 * sizeof(PairDev));
         h->d_table_cap = 0;
-        if (dev_malloc(h, (void**)&h->d_table, cap * sizeof(PairDev)) != hipSuccess) {
+        if (dev_malloc(h, (void**)&h->d_table, cap) != hipSuccess) {
             (void)hipGetLastError();
             h->d_table = nullptr;
             h->last.clear();
@@ -402,17 +409,17 @@ ff_status upload_table(ff_ctx* h, const std::vector<PairDev>& tab, hipStream_t s
     if (n > h->h_table_cap[k]) {
         if (h->h_table[k]) FF_HIP(h, hipHostFree(h->h_table[k]));
         h->h_table[k] = nullptr;
-        const size_t cap = std::max<size_t>(n, 16);
+        const size_t cap = std::max<size_t>(n, 16 * sizeof(PairDev));
         h->h_table_cap[k] = 0;
-        if (pinned_malloc(h, (void**)&h->h_table[k], cap * sizeof(PairDev)) != hipSuccess) {
+        if (pinned_malloc(h, (void**)&h->h_table[k], cap) != hipSuccess) {
             (void)hipGetLastError();
             h->h_table[k] = nullptr;
             return fail(h, FF_ERR_OOM, "pinned staging allocation failed");
         }
         h->h_table_cap[k] = cap;
     }
-    std::memcpy(h->h_table[k], tab.data(), n * sizeof(PairDev));
-    FF_HIP(h, hipMemcpyAsync(h->d_table, h->h_table[k], n * sizeof(PairDev), hipMemcpyHostToDevice, st));
+    std::memcpy(h->h_table[k], tab.data(), n);
+    FF_HIP(h, hipMemcpyAsync(h->d_table, h->h_table[k], n, hipMemcpyHostToDevice, st));
     FF_HIP(h, hipEventRecord(h->table_ev[k], st));
     h->last = tab;
     return FF_OK;
@@ -488,6 +495,10 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     const int L = p.levels, c = L - 1;
     const SearchConst sc = search_const(p);
     auto level_px = [&](int l) { return (size_t)plan0->W[l] * plan0->H[l]; };
+    auto work = [&](int ph, int l) {
+        return D.nitems[ph][l] ? LineWork{(const uint32_t*)((const char*)d + D.item_off[ph][l]), D.nitems[ph][l]}
+                               : LineWork{nullptr, 0};
+    };
     // a level's state for a debug stop: rows Wp apart on the device, packed [H][W] for the caller
     auto copy_state = [&](int l) {
         const LevelDev& V = tab0->lv[l];
@@ -560,12 +571,12 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                 const bool last = stop_here && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
                 FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census ? 1 : 0, d, n, l, t,
-                                                    std::min(upto, 3), scr, D.maxH[l], D.maxW[l], fuse && t == 0, st));
+                                                    std::min(upto, 3), scr, D.maxH[l], D.maxW[l], fuse && t == 0, work(0, l), st));
                 if (upto >= 4) {
                     // the column phase reads the row-major state; its result comes
                     // back row-major when the cross write applies, else from stateT
                     FF_TRACED(KN_COL, l, launch_line_phase(true, h->tune_ch[1][l], h->tune_wpb[1][l], h->tune_stg[1][l], census ? 1 : 0, d, n, l, t, upto, scr,
-                                                        D.maxW[l], D.maxH[l], 0, st));
+                                                        D.maxW[l], D.maxH[l], 0, work(1, l), st));
                     if (!line_cross_write(h->tune_wpb[1][l], D.maxH[l]))
                         FF_TRACED(KN_TRANS, l, launch_transpose_state(d, n, l, 0, D.maxW[l], D.maxH[l], st));
                 }
@@ -597,10 +608,10 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                 const bool last = stop_sub && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
                 FF_TRACED(KN_SUB_ROW, 0, launch_line_phase(false, 1, 8, 0, 2, d, n, 0, t, std::min(upto, 3), scs, D.maxH[0],
-                                                           D.maxW[0], t == 0 ? 1 : 0, st));
+                                                           D.maxW[0], t == 0 ? 1 : 0, LineWork{nullptr, 0}, st));
                 if (upto >= 4) {
                     FF_TRACED(KN_SUB_COL, 0, launch_line_phase(true, 1, 4, 0, 2, d, n, 0, t, upto, scs, D.maxW[0], D.maxH[0], 0,
-                                                               st));
+                                                               LineWork{nullptr, 0}, st));
                     if (!line_cross_write(4, D.maxH[0]))
                         FF_TRACED(KN_TRANS, 0, launch_transpose_state(d, n, 0, 0, D.maxW[0], D.maxH[0], st));
                 }
@@ -641,6 +652,8 @@ ff_status launch_graph(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t s
         key.push_back(D.maxW[l]);
         key.push_back(D.maxH[l]);
         key.push_back(D.maxPx[l]);
+        key.push_back(D.nitems[0][l]);
+        key.push_back(D.nitems[1][l]);
     }
     for (size_t i = 0; i < h->graphs.size(); ++i) {
         if (h->graphs[i].key != key) continue;
@@ -687,6 +700,33 @@ ff_status launch_graph(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t s
     return FF_OK;
 }
 
+// The line phases' work lists of a batch of uneven pairs: for each phase and
+// level, every (pair-direction, line block) that holds lines of its pair,
+// pair-direction-major, as pair-direction << 16 | block -- so a launch covers
+// each pair at its own size instead of the batch's largest (the blocks past a
+// smaller pair's size would only start and exit).  The lists depend on the
+// schedule's lines per block, so they are rebuilt when it changes.  Appended
+// to the table blob at 16-byte aligned offsets.
+void build_work_lists(const ff_ctx* h, const PairPlan* plans, int n, Dims& D, std::vector<char>& blob)
+{
+    for (int ph = 0; ph < 2; ++ph)
+        for (int l = 0; l < h->prm.levels; ++l) {
+            const int wpb = h->tune_wpb[ph][l];
+            size_t off = (blob.size() + 15) & ~(size_t)15;
+            size_t cnt = 0;
+            for (int i = 0; i < n; ++i) cnt += 2 * (size_t)(((ph ? plans[i].W[l] : plans[i].H[l]) + wpb - 1) / wpb);
+            blob.resize(off + cnt * sizeof(uint32_t));
+            uint32_t* it = (uint32_t*)(blob.data() + off);
+            for (int i = 0; i < n; ++i) {
+                const uint32_t nb = (uint32_t)(((ph ? plans[i].W[l] : plans[i].H[l]) + wpb - 1) / wpb);
+                for (uint32_t d = 0; d < 2; ++d)
+                    for (uint32_t b = 0; b < nb; ++b) *it++ = ((uint32_t)(2 * i) + d) << 16 | b;
+            }
+            D.nitems[ph][l] = (int)cnt;
+            D.item_off[ph][l] = off;
+        }
+}
+
 // Validate, size the workspace, upload the pair table, then enqueue the
 // search (graph replay unless tracing or stopping at an intermediate).
 ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop& stop)
@@ -696,8 +736,8 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     // the same pair array as the previous call, on the same arena: its
     // validation, plan and device table still hold (the table was uploaded
     // by that call and nothing has replaced it since)
-    if (!stop.active && h->last_valid && h->arena && h->arena == h->last_arena && (size_t)n == h->last_pairs.size() &&
-        std::memcmp(pairs, h->last_pairs.data(), (size_t)n * sizeof(ff_pair)) == 0) {
+    if (!stop.active && h->last_valid && h->arena && h->arena == h->last_arena && h->last_tune_gen == h->tune_gen &&
+        (size_t)n == h->last_pairs.size() && std::memcmp(pairs, h->last_pairs.data(), (size_t)n * sizeof(ff_pair)) == 0) {
         FF_HIP(h, hipSetDevice(h->device));
         if (h->run_any && st != h->run_stream) FF_HIP(h, hipStreamWaitEvent(st, h->run_done, 0));
         const Dims& D = h->last_dims;
@@ -727,11 +767,10 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     if (h->run_any && st != h->run_stream) FF_HIP(h, hipStreamWaitEvent(st, h->run_done, 0));
     std::vector<PairDev> tab(n);
     build_table(p, (char*)h->arena, pairs, n, tab.data(), plans.data());
-    s = upload_table(h, tab, st);
-    if (s != FF_OK) return s;
 
     Dims D;
     D.n = n;
+    bool uneven = false;
     for (int i = 0; i < n; ++i) {
         for (int l = 0; l < p.levels; ++l) {
             D.maxW[l] = std::max(D.maxW[l], plans[i].W[l]);
@@ -739,7 +778,15 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
             D.maxPx[l] = std::max(D.maxPx[l], plans[i].W[l] * plans[i].H[l]);
         }
         D.maxQ = std::max(D.maxQ, plans[i].nsx * plans[i].nsy);
+        uneven |= plans[i].W[0] != plans[0].W[0] || plans[i].H[0] != plans[0].H[0];
     }
+    // the device table: the pair entries, then for a batch of uneven pairs
+    // the line phases' work lists, one per phase and level
+    std::vector<char> blob((size_t)n * sizeof(PairDev));
+    std::memcpy(blob.data(), tab.data(), blob.size());
+    if (uneven) build_work_lists(h, plans.data(), n, D, blob);
+    s = upload_table(h, blob, st);
+    if (s != FF_OK) return s;
     if (!stop.active && !h->prof_on && h->use_graphs)
         s = launch_graph(h, h->d_table, D, st);
     else
@@ -752,6 +799,7 @@ ff_status run(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st, const Stop
     if (!stop.active) {
         h->last_dims = D;
         h->last_valid = true;
+        h->last_tune_gen = h->tune_gen;
         h->last_pairs.assign(pairs, pairs + n);
         h->last_arena = h->arena;
     }
@@ -884,6 +932,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
     for (const auto& c : kCand) {
         if (c[2] && (h->prm.flags & FF_COST_CENSUS)) continue;   // staged: descriptor cost only
         drop_graphs(h);
+        ++h->tune_gen;
         for (int ph = 0; ph < 2; ++ph)
             for (int l = 0; l < L; ++l) {
                 h->tune_ch[ph][l] = c[0];
@@ -923,6 +972,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
             h->tune_wpb[ph][l] = bc[ph][l][1];
             h->tune_stg[ph][l] = bc[ph][l][2];
         }
+    ++h->tune_gen;
     h->prof_on = was_on;
     drop_graphs(h);
     return FF_OK;
@@ -970,7 +1020,7 @@ ff_ctx* make_ctx(const ff_params& p, int device, ff_ctx* root, ff_status* st)
             *st = FF_ERR_OOM;
             return nullptr;
         }
-        h->h_table_cap[k] = 16;
+        h->h_table_cap[k] = 16 * sizeof(PairDev);
     }
     const char* g = std::getenv("FF_GRAPHS");
     h->use_graphs = !(g && g[0] == '0');
@@ -1270,6 +1320,7 @@ ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n)
             h->tune_wpb[ph][l] = cfg[(ph * L + l) * 3 + 1];
             h->tune_stg[ph][l] = cfg[(ph * L + l) * 3 + 2];
         }
+    ++h->tune_gen;
     drop_graphs(h);
     return FF_OK;
 }
