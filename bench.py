@@ -31,6 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # (chunks per window, lines per block, staged) for row levels 0..3, then col
 # levels 0..3.  Any schedule gives identical outputs; --autotune re-tunes.
 SCHEDULE_C1 = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0, 1, 2, 0]
+# The same for the Census cost on the Sintel-shaped batch (used by the
+# profiler legs, which do not autotune).
+SCHEDULE_CENSUS = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0, 1, 4, 0]
 
 # HBM traffic of the col-phase kernel per launch (average over the 8
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
@@ -513,6 +516,40 @@ def plain_bench(torch, m, pairs, outs, rounds, batched_ms_per_pair):
             "batched_ms_per_pair": batched_ms_per_pair}
 
 
+def profiler_leg(torch, ff, leg, steps):
+    """A short fixed-schedule run of one leg, for rocprofv3 runs: `census`
+    (64 Sintel-shaped 1024x436 RGB pairs, Census cost, eps 7), `subpix` (the
+    64-pair 1242x375 batch with one quarter-pixel refinement iteration) or
+    `c4` (the 4096-pair config-4 batch).  Prints one JSON line."""
+    from paper_1805_03517_amd import synth
+    if leg == "census":
+        base = [synth.config2(seed=30 + k)[:2] for k in range(8)]
+        pairs = [(torch.from_numpy(base[k % 8][0]).cuda(), torch.from_numpy(base[k % 8][1]).cuda()) for k in range(64)]
+        m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=7, seed=0x5EED, cost="census")
+        m.set_tuning(SCHEDULE_CENSUS)
+    elif leg == "subpix":
+        _, pairs = make_inputs(torch, 64, 8)
+        m = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, sub_iters=1,
+                       sub_radius=2)
+        m.set_tuning(SCHEDULE_C1)
+    elif leg == "c4":
+        pairs = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b, _ in synth.config4_batch(seed=4, n=4096)]
+        m = ff.Matcher(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
+    else:
+        raise SystemExit(f"unknown leg {leg}")
+    prep = m.prepare_batch(pairs)
+    for _ in range(2):
+        m.match_prepared(prep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.match_prepared(prep)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    m.close()
+    print(json.dumps({"leg": leg, "pairs": len(pairs), "ms_per_call": 1000 * dt}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -527,9 +564,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the per-pair ff_match_pair leg")
     ap.add_argument("--autotune", action="store_true", help="re-tune the line-kernel schedule first")
     ap.add_argument("--default-schedule", action="store_true", help="the handle's default schedule")
+    ap.add_argument("--schedule", type=str, default="",
+                    help="comma-separated line-kernel schedule (6 x levels ints, see ff_tune_set) instead of the tuned one")
     ap.add_argument("--seednn-only", action="store_true",
                     help="only time the seed search at the large shape (for counter runs)")
     ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")
+    ap.add_argument("--leg", choices=["census", "subpix", "c4"],
+                    help="only a short fixed-schedule run of that leg (for profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-census", action="store_true", help="skip the Census-cost leg")
@@ -557,6 +598,11 @@ def main():
         pair = (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
         print(json.dumps(seednn_bench(torch, ff, pair, (1, 1.0, 0, 0.0))["large_shape"]), flush=True)
         return
+    if args.leg:
+        import torch
+        from paper_1805_03517_amd import ff
+        profiler_leg(torch, ff, args.leg, max(1, args.steps))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pairs are independent and a "
               "multi-GPU run would shard them across processes, which is not implemented", file=sys.stderr)
@@ -579,6 +625,8 @@ def main():
     if args.autotune:
         print("[bench] autotuning the line-kernel schedule on this batch", file=sys.stderr, flush=True)
         m.autotune(pairs, outs=outs)
+    elif args.schedule:
+        m.set_tuning([int(v) for v in args.schedule.split(",")])
     elif not args.default_schedule:
         m.set_tuning(SCHEDULE_C1)
     tuning = m.tuning()
