@@ -517,7 +517,8 @@ def plain_bench(torch, m, pairs, outs, rounds, batched_ms_per_pair):
 
 
 def profiler_leg(torch, ff, leg, steps):
-    """A short fixed-schedule run of one leg, for rocprofv3 runs: `census`
+    """A short fixed-schedule run of one leg, for rocprofv3 runs (`serve`,
+    bench.py's serving leg alone, is dispatched in main): `census`
     (64 Sintel-shaped 1024x436 RGB pairs, Census cost, eps 7), `subpix` (the
     64-pair 1242x375 batch with one quarter-pixel refinement iteration) or
     `c4` (the 4096-pair config-4 batch).  Prints one JSON line."""
@@ -569,7 +570,7 @@ def main():
     ap.add_argument("--seednn-only", action="store_true",
                     help="only time the seed search at the large shape (for counter runs)")
     ap.add_argument("--c4-pairs", type=int, default=4096, help="config-4 batch size (0 skips it)")
-    ap.add_argument("--leg", choices=["census", "subpix", "c4"],
+    ap.add_argument("--leg", choices=["census", "subpix", "c4", "serve"],
                     help="only a short fixed-schedule run of that leg (for profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
@@ -601,7 +602,10 @@ def main():
     if args.leg:
         import torch
         from paper_1805_03517_amd import ff
-        profiler_leg(torch, ff, args.leg, max(1, args.steps))
+        if args.leg == "serve":
+            print(json.dumps(serve_bench(torch, ff, args.serve_requests, lanes=4, budget=64 << 30)), flush=True)
+        else:
+            profiler_leg(torch, ff, args.leg, max(1, args.steps))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pairs are independent and a "

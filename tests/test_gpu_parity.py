@@ -506,3 +506,39 @@ def test_config4_style_batch_equals_per_pair(torch, ffm, orc):
         _compare_outputs(orc.match(a, b, orc.params(levels=3)), ob[k], f"config4 member {k}")
     mb.close()
     mp.close()
+
+
+@pytest.mark.parametrize("sched", ["default", "generic", "pipelined", "narrow"])
+def test_uneven_batch_work_lists_at_edge_shapes(torch, ffm, orc, sched):
+    """A batch of 36 uneven pairs -- enough for the line phases' device work
+    lists -- mixing extreme shapes (2 px sides, 300 px lines, one pixel past
+    a 64-px window) under several schedules: every member equals its own
+    ff_match_pair call bit for bit, and four equal the oracle."""
+    rng = np.random.default_rng(77)
+    shapes = [(2, 2), (2, 300), (300, 2), (65, 9), (9, 65), (129, 3), (64, 64), (3, 129)]
+    while len(shapes) < 36:
+        shapes.append((int(rng.integers(2, 301)), int(rng.integers(2, 241))))
+    pairs = []
+    for k, (W, H) in enumerate(shapes):
+        d = (int(rng.integers(-5, 6)), int(rng.integers(-5, 6)))
+        pairs.append(synth.translated_pair(np.random.default_rng(500 + k), W, H, d=d,
+                                           rect=(min(8, W // 2), min(6, H // 2)), rect_d=(2, -1))[:2])
+    L = 2
+    tuning = {"default": None, "generic": [4, 4, 0] * (2 * L), "pipelined": [1, 8, 0] * L + [2, 4, 0] * L,
+              "narrow": [1, 2, 0] * L + [2, 2, 0] * L}[sched]
+    mb, mp = ffm.Matcher(levels=L), ffm.Matcher(levels=L)
+    if tuning:
+        mb.set_tuning(tuning)
+        mp.set_tuning(tuning)
+    dev = [(_dev(torch, a), _dev(torch, b)) for a, b in pairs]
+    say("36 uneven pairs with edge shapes, schedule", sched)
+    ob = mb.match_batch(dev)
+    op = [mp.match(a, b) for a, b in dev]
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(ob, op)):
+        for key in x:
+            assert torch.equal(x[key], y[key]), (k, shapes[k], key)
+    for k in (0, 2, 3, 20):
+        _compare_outputs(orc.match(pairs[k][0], pairs[k][1], orc.params(levels=L)), ob[k], f"edge batch member {k}")
+    mb.close()
+    mp.close()

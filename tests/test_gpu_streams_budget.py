@@ -120,9 +120,11 @@ def test_repeated_pair_array_after_other_calls(torch, ffm, orc):
     between (another batch, a single pair, a debug stage, a new schedule)
     must not leave it stale.  Every repeat equals the first result, and the
     first equals the oracle."""
+    # 40 uneven pairs: enough for the line phases' device work lists, which
+    # are part of the table and depend on the schedule
     rng = np.random.default_rng(401)
     pairs = []
-    for k in range(5):
+    for k in range(40):
         W, H = int(rng.integers(64, 220)), int(rng.integers(64, 180))
         d = (int(rng.integers(-16, 17)), int(rng.integers(-16, 17)))
         pairs.append(synth.translated_pair(np.random.default_rng(410 + k), W, H, d=d)[:2])
@@ -134,8 +136,8 @@ def test_repeated_pair_array_after_other_calls(torch, ffm, orc):
     torch.cuda.synchronize()
     first = [{k: v.clone() for k, v in o.items()} for o in prep.outs]
     p = orc.params(levels=3)
-    for k, (a, b) in enumerate(pairs):
-        _same(orc.match(a, b, p), first[k], f"member {k}")
+    for k in (0, 17, 39):
+        _same(orc.match(pairs[k][0], pairs[k][1], p), first[k], f"member {k}")
 
     def again(tag):
         say("repeated pair array after", tag)
@@ -150,7 +152,7 @@ def test_repeated_pair_array_after_other_calls(torch, ffm, orc):
 
     again("itself (graph capture)")
     again("itself (graph replay)")
-    m.match_batch(dev[::-1][:3])
+    m.match_batch(dev[::-1][:35])
     again("another batch")
     m.match(*dev[2])
     again("a single pair")
