@@ -119,7 +119,8 @@ def cpu_baseline(base, n_pairs, threads):
     """The oracle as it stands, single-threaded, on the first n_pairs pairs;
     then, when threads > 1, one pair per thread on that many host cores at
     once (the oracle's C entry point releases the GIL and keeps no global
-    state, so the threads run it side by side unchanged)."""
+    state, so the threads run it side by side unchanged); then, for context,
+    two Sintel-shaped 1024x436 pairs single-threaded (eps 7)."""
     import oracle
     oracle.build(force=not os.path.exists(oracle._LIB))
     prm = oracle.params(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED)
@@ -140,6 +141,16 @@ def cpu_baseline(base, n_pairs, threads):
         out["all_cores"] = {"value": threads * W0 * H0 / dt, "unit": "px/s", "cores": threads,
                             "sample": f"{threads} pairs, one per thread", "pairs_per_s": threads / dt,
                             "seconds": dt}
+    from paper_1805_03517_amd import synth
+    prm2 = oracle.params(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=7, seed=0x5EED)
+    c2 = [synth.config2(seed=30 + k)[:2] for k in range(2)]
+    t0 = time.perf_counter()
+    for a, b in c2:
+        oracle.match(a, b, prm2)
+    dt = time.perf_counter() - t0
+    out["sintel_1024x436"] = {"value": 2 * 1024 * 436 / dt, "unit": "px/s", "cores": 1,
+                              "sample": "2 Sintel-shaped 1024x436 RGB pairs, whole search, one thread",
+                              "pairs_per_s": 2 / dt, "seconds": dt}
     return out
 
 
@@ -401,6 +412,21 @@ def census_bench(torch, ff, n_pairs, distinct, steps):
         prof = m.profile_read()
         m.profile(False)
         m.close()
+        plain = None
+        if cost == "wh":
+            # the plain path on the same batch: one ff_match_pair per pair
+            m2 = ff.Matcher(levels=LEVELS, seed_stride=3, iters=2, rs_radius=16, fb_eps=7, seed=0x5EED, cost=cost)
+            m2.set_tuning(tuning)
+            for (a, b), o in zip(pairs[:4], outs[:4]):
+                m2.match(a, b, out=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for (a, b), o in zip(pairs, outs):
+                m2.match(a, b, out=o)
+            torch.cuda.synchronize()
+            dtp = time.perf_counter() - t0
+            m2.close()
+            plain = {"pairs_per_s": n_pairs / dtp, "px_per_s": n_pairs * W * H / dtp}
         n, ms = prof["col_phase"]
         per_px = CEN_COL_BYTES_PER_PX if cost == "census" else COL_BYTES_PER_PX
         avg_bytes = per_px * px_all * 2 * n_pairs * 2 / (2 * LEVELS)
@@ -411,6 +437,8 @@ def census_bench(torch, ff, n_pairs, distinct, steps):
                      "col_phase": {"avg_us": avg_s * 1e6, "algorithmic_bytes_per_launch": avg_bytes,
                                    "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
                      "kernels": {k: round(1000.0 * v[1] / max(v[0], 1), 1) for k, v in prof.items()}}
+        if plain:
+            out[cost]["plain"] = plain
     return out
 
 
