@@ -78,6 +78,12 @@ typedef enum {
 #define FF_SECOND_CHECK 4u  /* two consistency checks (Sec. 3.1): the search runs a
                                second time keyed by seed2, and a match must also be
                                consistent with that search's inverse field        */
+#define FF_SECOND_PARAMS 16u /* with FF_SECOND_CHECK: the second search also runs
+                               with its own matching parameters (Sec. 3.1: the
+                               inverse fields of the two checks come from
+                               searches with different parameters) -- iters2
+                               iterations per level and random-search radius
+                               rs_radius2 -- instead of the first search's   */
 #define FF_SUBPIXEL 8u      /* sub-pixel refinement (Sec. 3.1): after the integer
                                search, sub_iters more iterations at level 0 on flows
                                in quarter pixels, the cost of a quarter-pixel target
@@ -101,7 +107,7 @@ typedef struct {
     uint64_t seed;          /* random-search key                                 */
     uint64_t hbm_budget;    /* cap on workspace bytes; 0 = no cap                */
     uint32_t flags;         /* FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK |
-                               FF_SUBPIXEL, or 0                               */
+                               FF_SECOND_PARAMS | FF_SUBPIXEL, or 0            */
     int32_t  sparse_min;    /* s: matches a 3x3 block needs to keep one, 1..9
                                (7); read only with FF_SPARSIFY                 */
     uint64_t seed2;         /* random-search key of the second search; read
@@ -109,6 +115,10 @@ typedef struct {
     int32_t  sub_iters;     /* FF_SUBPIXEL: refinement iterations, 1..16 (1)    */
     int32_t  sub_radius;    /* FF_SUBPIXEL: random-search radius in quarter
                                pixels, 0..64 (2: trials at 1/2 and 1/4 px)     */
+    int32_t  iters2;        /* FF_SECOND_PARAMS: the second search's iterations
+                               per level, 0..64                               */
+    int32_t  rs_radius2;    /* FF_SECOND_PARAMS: its random-search radius,
+                               0..1024                                         */
 } ff_params;
 
 /* One image pair and its outputs.  Both frames are [H][W][C] uint8,

@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("rs_radius", ctypes.c_int32),
                 ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64), ("cost_kind", ctypes.c_int32),
                 ("two_checks", ctypes.c_int32), ("seed2", ctypes.c_uint64),
-                ("sub_iters", ctypes.c_int32), ("sub_radius", ctypes.c_int32)]
+                ("sub_iters", ctypes.c_int32), ("sub_radius", ctypes.c_int32),
+                ("second_params", ctypes.c_int32), ("iters2", ctypes.c_int32), ("rs_radius2", ctypes.c_int32)]
 
 
 COST_WH, COST_CENSUS = 0, 1
@@ -95,9 +96,13 @@ def _p(a: np.ndarray):
 
 
 def params(levels=3, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED, cost_kind=COST_WH,
-           two_checks=0, seed2=0, sub_iters=0, sub_radius=2) -> Params:
+           two_checks=0, seed2=0, sub_iters=0, sub_radius=2, iters2=None, rs_radius2=None) -> Params:
+    """iters2 / rs_radius2 (with two_checks): the second search's own
+    iterations and random-search radius (None: the first search's)."""
+    second = iters2 is not None or rs_radius2 is not None
     return Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, cost_kind, two_checks, seed2,
-                  sub_iters, sub_radius)
+                  sub_iters, sub_radius, 1 if second else 0, iters if iters2 is None else iters2,
+                  rs_radius if rs_radius2 is None else rs_radius2)
 
 
 def gray(img: np.ndarray) -> np.ndarray:

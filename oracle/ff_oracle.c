@@ -611,6 +611,7 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
         return -1;
     if (p->sub_iters < 0 || (p->sub_iters > 0 && (p->cost_kind != FFO_COST_WH || p->sub_radius < 0 || W > 2048 || H > 2048)))
         return -1;
+    if (p->second_params && (p->iters2 < 0 || p->rs_radius2 < 0)) return -1;
     if (W < 1 || H < 1 || (W >> (p->levels - 1)) < 1 || (H >> (p->levels - 1)) < 1) return -1;
 
     int L = p->levels;
@@ -664,6 +665,10 @@ int ffo_match(const ffo_params* p, const uint8_t* img1, const uint8_t* img2,
          * must be consistent with both inverse fields (Sec. 3.1)          */
         ffo_params p2 = *p;
         p2.seed = p->seed2;
+        if (p->second_params) {          /* other matching parameters too */
+            p2.iters = p->iters2;
+            p2.rs_radius = p->rs_radius2;
+        }
         size_t n = (size_t)W * H;
         int16_t* f2 = (int16_t*)malloc(sizeof(int16_t) * 2 * n);
         int16_t* b2 = (int16_t*)malloc(sizeof(int16_t) * 2 * n);

@@ -38,6 +38,11 @@ typedef struct {
                                (flows, errors and eps then in quarter pixels;
                                descriptor cost only)                          */
     int32_t  sub_radius;    /* its random-search radius in quarter pixels      */
+    int32_t  second_params; /* with two_checks: 1 = the second search runs
+                               iters2 iterations per level at random-search
+                               radius rs_radius2 (0 = the first search's)    */
+    int32_t  iters2;
+    int32_t  rs_radius2;
 } ffo_params;
 
 #define FFO_COST_WH     0   /* SAD of the 16 Walsh-Hadamard coefficients     */

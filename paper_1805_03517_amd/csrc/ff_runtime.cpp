@@ -223,8 +223,13 @@ ff_status validate_params(ff_ctx* h, const ff_params& p)
     if (p.iters < 0 || p.iters > 64) return fail(h, FF_ERR_INVALID, "iters must be in 0..64");
     if (p.rs_radius < 0 || p.rs_radius > 1024) return fail(h, FF_ERR_INVALID, "rs_radius must be in 0..1024");
     if (p.fb_eps < 0 || p.fb_eps > 1024) return fail(h, FF_ERR_INVALID, "fb_eps must be in 0..1024");
-    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK | FF_SUBPIXEL))
+    if (p.flags & ~(FF_SPARSIFY | FF_COST_CENSUS | FF_SECOND_CHECK | FF_SECOND_PARAMS | FF_SUBPIXEL))
         return fail(h, FF_ERR_INVALID, "unknown flag bits");
+    if (p.flags & FF_SECOND_PARAMS) {
+        if (!(p.flags & FF_SECOND_CHECK)) return fail(h, FF_ERR_INVALID, "FF_SECOND_PARAMS needs FF_SECOND_CHECK");
+        if (p.iters2 < 0 || p.iters2 > 64) return fail(h, FF_ERR_INVALID, "iters2 must be in 0..64");
+        if (p.rs_radius2 < 0 || p.rs_radius2 > 1024) return fail(h, FF_ERR_INVALID, "rs_radius2 must be in 0..1024");
+    }
     if (p.flags & FF_SUBPIXEL) {
         if (p.flags & FF_COST_CENSUS) return fail(h, FF_ERR_INVALID, "FF_SUBPIXEL needs the descriptor cost");
         if (p.sub_iters < 1 || p.sub_iters > 16) return fail(h, FF_ERR_INVALID, "sub_iters must be in 1..16");
@@ -549,17 +554,26 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
     // the first search's level-0 state is saved (debug stops name the first).
     const bool second = (p.flags & FF_SECOND_CHECK) != 0;
     const bool subpix = (p.flags & FF_SUBPIXEL) != 0;
+    // the second search: keyed by seed2, and with FF_SECOND_PARAMS run with
+    // its own iteration count and random-search radius
     SearchConst sc2 = sc;
     sc2.key0 = (uint32_t)p.seed2;
     sc2.key1 = (uint32_t)(p.seed2 >> 32);
+    if (p.flags & FF_SECOND_PARAMS) {
+        sc2.iters = p.iters2;
+        sc2.radius = p.rs_radius2;
+        sc2.trials = 0;
+        while ((p.rs_radius2 >> sc2.trials) > 0) ++sc2.trials;
+    }
     for (int run_k = 0; run_k < (second ? 2 : 1); ++run_k) {
         const SearchConst& scr = run_k ? sc2 : sc;
+        const int iters = scr.iters;
         if (run_k == 1) FF_TRACED(KN_SAVE, 0, launch_save_state(d, n, D.maxPx[0], st));
         for (int l = c; l >= 0; --l) {
             const bool stop_here = run_k == 0 && stop.active && stop.st.kind == FF_STAGE_STATE && stop.st.level == l;
             // the row phase of iteration 0 takes over the init when its
             // schedule allows (and no stop asks for the init state itself)
-            const bool fuse = p.iters > 0 && line_fused_init(h->tune_ch[0][l], h->tune_stg[0][l], scr) &&
+            const bool fuse = iters > 0 && line_fused_init(h->tune_ch[0][l], h->tune_stg[0][l], scr) &&
                               !(stop_here && stop.st.step == 0);
             if (!fuse)
                 FF_TRACED(KN_INIT, l, launch_init(d, n, l, l == c ? 1 : 0, p.seed_stride, census ? 1 : 0, D.maxPx[l], st));
@@ -567,7 +581,7 @@ ff_status enqueue(ff_ctx* h, const PairDev* d, const Dims& D, hipStream_t st, co
                 FF_HIP(h, copy_state(l));
                 return FF_OK;
             }
-            for (int t = 0; t < p.iters; ++t) {
+            for (int t = 0; t < iters; ++t) {
                 const bool last = stop_here && stop.st.iter == t;
                 const int upto = last ? stop.st.step : 7;
                 FF_TRACED(KN_ROW, l, launch_line_phase(false, h->tune_ch[0][l], h->tune_wpb[0][l], h->tune_stg[0][l], census ? 1 : 0, d, n, l, t,

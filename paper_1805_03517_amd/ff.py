@@ -18,6 +18,7 @@ FF_SPARSIFY = 1                                  # params.flags: 3x3-block spars
 FF_COST_CENSUS = 2                               # params.flags: 7x7 Census (Hamming) matching cost
 FF_SECOND_CHECK = 4                              # params.flags: second consistency check (search keyed by seed2)
 FF_SUBPIXEL = 8                                  # params.flags: quarter-pixel refinement at level 0
+FF_SECOND_PARAMS = 16                            # params.flags: the second search's own iters / radius
 STAGE_GRAY, STAGE_PYRAMID, STAGE_DESC, STAGE_SEEDS, STAGE_STATE, STAGE_CENSUS = range(6)
 INF = 2**31 - 1
 
@@ -40,7 +41,8 @@ class Params(ctypes.Structure):
                 ("fb_eps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("hbm_budget", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("sparse_min", ctypes.c_int32), ("seed2", ctypes.c_uint64),
-                ("sub_iters", ctypes.c_int32), ("sub_radius", ctypes.c_int32)]
+                ("sub_iters", ctypes.c_int32), ("sub_radius", ctypes.c_int32),
+                ("iters2", ctypes.c_int32), ("rs_radius2", ctypes.c_int32)]
 
 
 class Pair(ctypes.Structure):
@@ -131,7 +133,8 @@ class Matcher:
     [H, W] (gray) or [H, W, 3] (RGB), contiguous."""
 
     def __init__(self, levels=4, seed_stride=3, iters=2, rs_radius=16, fb_eps=1, seed=0x5EED,
-                 hbm_budget=0, device=0, sparse_min=0, cost="wh", seed2=None, sub_iters=0, sub_radius=2):
+                 hbm_budget=0, device=0, sparse_min=0, cost="wh", seed2=None, sub_iters=0, sub_radius=2,
+                 iters2=None, rs_radius2=None):
         """sparse_min > 0 turns on the 3x3-block sparsification (FF_SPARSIFY)
         with that minimum number of matches s; outputs then include
         sparse_f / sparse_b and the consistency errors fberr_f / fberr_b.
@@ -140,17 +143,22 @@ class Matcher:
         against the inverse fields of a search keyed by seed2 (FF_SECOND_CHECK).
         sub_iters > 0 adds that many quarter-pixel refinement iterations at
         level 0 (FF_SUBPIXEL, random-search radius sub_radius quarter pixels);
-        flows are then in quarter pixels and fberr in 1/16 px^2."""
+        flows are then in quarter pixels and fberr in 1/16 px^2.  iters2 /
+        rs_radius2 (with seed2) give the second search its own iterations and
+        random-search radius (FF_SECOND_PARAMS); None = the first search's."""
         if cost not in ("wh", "census"):
             raise FFError(FF_ERR_INVALID, "cost must be 'wh' or 'census'")
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
         self.sparse = sparse_min > 0
+        second = iters2 is not None or rs_radius2 is not None
         flags = ((FF_SPARSIFY if self.sparse else 0) | (FF_COST_CENSUS if cost == "census" else 0) |
-                 (FF_SECOND_CHECK if seed2 is not None else 0) | (FF_SUBPIXEL if sub_iters > 0 else 0))
+                 (FF_SECOND_CHECK if seed2 is not None else 0) | (FF_SUBPIXEL if sub_iters > 0 else 0) |
+                 (FF_SECOND_PARAMS if second else 0))
         self.params = Params(levels, seed_stride, iters, rs_radius, fb_eps, seed, hbm_budget, flags, sparse_min,
-                             seed2 if seed2 is not None else 0, sub_iters, sub_radius)
+                             seed2 if seed2 is not None else 0, sub_iters, sub_radius,
+                             iters if iters2 is None else iters2, rs_radius if rs_radius2 is None else rs_radius2)
         h = ctypes.c_void_p()
         st = lib().ff_create(ctypes.byref(self.params), device, ctypes.byref(h))
         if st != FF_OK:

@@ -97,3 +97,34 @@ def test_second_check_batch_and_same_key(torch, ffm, orc):
         assert torch.equal(r1[k], r2[k]), k
     one.close()
     same.close()
+
+
+@pytest.mark.parametrize("cfg,iters2,radius2", [("c0", 1, 4), ("c0", 3, 40), ("c1", 0, 16), ("c1", 3, 8)])
+def test_second_check_with_its_own_parameters(torch, ffm, orc, cfg, iters2, radius2):
+    """FF_SECOND_PARAMS: the second search runs iters2 iterations per level
+    at random-search radius rs_radius2 (Sec. 3.1: the inverse fields of the
+    two checks come from differently parameterised searches); flows, costs,
+    errors and masks bit-exact against the oracle."""
+    if cfg == "c0":
+        i1, i2, _ = synth.config0()
+        L = 3
+    else:
+        i1, i2, _ = synth.config1(seed=64)
+        L = 4
+    seed2 = 0xBEEF
+    say("second check with its own parameters", cfg, "iters2", iters2, "radius2", radius2)
+    m = ffm.Matcher(levels=L, seed2=seed2, iters2=iters2, rs_radius2=radius2)
+    out = m._outputs(i1.shape[0], i1.shape[1])
+    out["fberr_f"] = torch.empty(i1.shape[:2], dtype=torch.int32, device="cuda")
+    out["fberr_b"] = torch.empty(i1.shape[:2], dtype=torch.int32, device="cuda")
+    got = m.match(torch.from_numpy(i1).cuda(), torch.from_numpy(i2).cuda(), out=out)
+    torch.cuda.synchronize()
+    p = orc.params(levels=L, two_checks=1, seed2=seed2, iters2=iters2, rs_radius2=radius2)
+    r = orc.match(i1, i2, p)
+    alt = orc.match(i1, i2, orc.params(levels=L, seed=seed2, iters=iters2, rs_radius=radius2))
+    r["fberr_f"] = orc.fb_error2(r["flow_f"], r["cost_f"], r["flow_b"], r["cost_b"], alt["flow_b"], alt["cost_b"])
+    r["fberr_b"] = orc.fb_error2(r["flow_b"], r["cost_b"], r["flow_f"], r["cost_f"], alt["flow_f"], alt["cost_f"])
+    _check(r, got, f"second check with own parameters {cfg}")
+    m.close()
+    with pytest.raises(ffm.FFError):
+        ffm.Matcher(levels=L, iters2=2)                # needs the second check

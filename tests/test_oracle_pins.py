@@ -238,6 +238,31 @@ def test_two_checks_in_the_search(orc):
     assert np.array_equal(two["mask_f"], (e <= 1).astype(np.uint8))
 
 
+def test_two_checks_with_the_second_search_s_own_parameters(orc):
+    """With its own iteration count and random-search radius the second
+    search is exactly the search run alone with those parameters (and that
+    key): the two-check mask is err <= eps^2 against that search's inverse
+    field; the first search's flows and costs are untouched; and the
+    parameters matter (the masks differ from the same-parameter check's)."""
+    i1, i2, _ = synth.config0()
+    one = orc.match(i1, i2, orc.params(levels=3))
+    same = orc.match(i1, i2, orc.params(levels=3, two_checks=1, seed2=0xBEEF))
+    own = orc.match(i1, i2, orc.params(levels=3, two_checks=1, seed2=0xBEEF, iters2=1, rs_radius2=3))
+    for k in ("flow_f", "cost_f", "flow_b", "cost_b"):
+        assert np.array_equal(one[k], own[k]), k
+    alt = orc.match(i1, i2, orc.params(levels=3, seed=0xBEEF, iters=1, rs_radius=3))
+    for fwd in (True, False):
+        F, cF, B, cB, B2, cB2 = (("flow_f", "cost_f", "flow_b", "cost_b", "flow_b", "cost_b") if fwd else
+                                 ("flow_b", "cost_b", "flow_f", "cost_f", "flow_f", "cost_f"))
+        e = orc.fb_error2(one[F], one[cF], one[B], one[cB], alt[B2], alt[cB2])
+        assert np.array_equal(own["mask_f" if fwd else "mask_b"], (e <= 1).astype(np.uint8))
+    assert not np.array_equal(own["mask_f"], same["mask_f"])
+    # with the first search's own parameters given explicitly nothing changes
+    expl = orc.match(i1, i2, orc.params(levels=3, two_checks=1, seed2=0xBEEF, iters2=2, rs_radius2=16))
+    for k in same:
+        assert np.array_equal(same[k], expl[k]), k
+
+
 def _read_sparse_fixture():
     lines = [l.strip() for l in open(os.path.join(HERE, "golden", "sparsify_3x3_example.txt"))]
     rows = [l for l in lines if l and not l.startswith("#") and not l.startswith("s ")]
