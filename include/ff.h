@@ -233,9 +233,13 @@ uint64_t ff_workspace_bytes(ff_handle h, const ff_pair* pairs, int32_t n);
  * ff_serve_config: (re)configure, 1 <= lanes <= 16, lane_bytes >= 1 MiB;
  *   FF_ERR_BUSY while requests are queued or running.  Without it the first ff_submit configures 4 lanes of
  *   hbm_budget / 4 bytes (4 GiB each when no budget is set).
- * ff_submit: FF_ERR_BUDGET when the pair alone exceeds lane_bytes.
+ * ff_submit: FF_OK once the pair is queued; FF_ERR_BUDGET when the pair
+ *   alone exceeds lane_bytes, FF_ERR_INVALID for a bad pair (not queued).
  * ff_poll: non-blocking; writes up to `max` finished tags (completion
- *   order), returns how many, or -1 on error.
+ *   order), returns how many, or -1 on error (ff_last_error names it).
+ *   A cohort that cannot start (an allocation or launch failure on its
+ *   lane) goes back to the head of the queue unchanged, so no submitted
+ *   pair is lost: every ff_poll tries again, returning -1 while it fails.
  * ff_serve_inflight: queued + running pairs, or -1.                        */
 ff_status ff_serve_config(ff_handle h, int32_t lanes, uint64_t lane_bytes);
 ff_status ff_submit(ff_handle h, const ff_pair* pair, uint64_t tag, void* stream);

@@ -393,6 +393,10 @@ ff_status upload_table(ff_ctx* h, const std::vector<char>& tab, hipStream_t st)
     const size_t n = tab.size();                       // bytes
     if (h->last.size() == n && std::memcmp(h->last.data(), tab.data(), n) == 0)
         return FF_OK;                                  // device table already current
+    // from here until the copy is enqueued the device table's contents are
+    // unknown (a new allocation, or a copy that failed): forget them, so a
+    // later call never skips its upload on the strength of a stale record
+    h->last.clear();
     if (n > h->d_table_cap) {
         if (h->d_table) {
             FF_HIP(h, hipDeviceSynchronize());
@@ -404,7 +408,6 @@ ff_status upload_table(ff_ctx* h, const std::vector<char>& tab, hipStream_t st)
         if (dev_malloc(h, (void**)&h->d_table, cap) != hipSuccess) {
             (void)hipGetLastError();
             h->d_table = nullptr;
-            h->last.clear();
             return fail(h, FF_ERR_OOM, "hipMalloc of the device pair table failed");
         }
         h->d_table_cap = cap;
@@ -412,15 +415,17 @@ ff_status upload_table(ff_ctx* h, const std::vector<char>& tab, hipStream_t st)
     const int k = (int)(h->staging_next++ % ff_ctx::kStaging);
     FF_HIP(h, hipEventSynchronize(h->table_ev[k]));   // the copy that last read slot k is done
     if (n > h->h_table_cap[k]) {
-        if (h->h_table[k]) FF_HIP(h, hipHostFree(h->h_table[k]));
-        h->h_table[k] = nullptr;
+        // the slot keeps its old buffer until the larger one exists, so every
+        // slot always holds at least the 16 pairs it was created with (the
+        // allocation-free entry point relies on that)
         const size_t cap = std::max<size_t>(n, 16 * sizeof(PairDev));
-        h->h_table_cap[k] = 0;
-        if (pinned_malloc(h, (void**)&h->h_table[k], cap) != hipSuccess) {
+        char* grown = nullptr;
+        if (pinned_malloc(h, (void**)&grown, cap) != hipSuccess) {
             (void)hipGetLastError();
-            h->h_table[k] = nullptr;
             return fail(h, FF_ERR_OOM, "pinned staging allocation failed");
         }
+        if (h->h_table[k]) (void)hipHostFree(h->h_table[k]);
+        h->h_table[k] = grown;
         h->h_table_cap[k] = cap;
     }
     std::memcpy(h->h_table[k], tab.data(), n);
@@ -949,6 +954,21 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
             bc[ph][l][2] = h->tune_stg[ph][l];
         }
     const bool was_on = h->prof_on;
+    // on failure the handle goes back to the schedule it had
+    auto restore = [&](ff_status s) {
+        for (int ph = 0; ph < 2; ++ph)
+            for (int l = 0; l < L; ++l) {
+                h->tune_ch[ph][l] = bc[ph][l][0];
+                h->tune_wpb[ph][l] = bc[ph][l][1];
+                h->tune_stg[ph][l] = bc[ph][l][2];
+            }
+        ++h->tune_gen;
+        h->prof_on = was_on;
+        drop_graphs(h);
+        return s;
+    };
+    int orig[2][kMaxLevels][3];
+    std::memcpy(orig, bc, sizeof orig);
     std::vector<Timed> discard;
     (void)collect_profile(h, discard);
     for (const auto& c : kCand) {
@@ -966,15 +986,15 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
             ff_status s = run(h, pairs, n, st, Stop{});
             h->prof_on = false;
             if (s != FF_OK) {
-                h->prof_on = was_on;
-                return s;
+                std::memcpy(bc, orig, sizeof orig);
+                return restore(s);
             }
         }
         std::vector<Timed> recs;
         ff_status s = collect_profile(h, recs);
         if (s != FF_OK) {
-            h->prof_on = was_on;
-            return s;
+            std::memcpy(bc, orig, sizeof orig);
+            return restore(s);
         }
         double t[2][kMaxLevels] = {{0}};
         for (const Timed& r : recs) {
@@ -988,16 +1008,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
                     for (int k = 0; k < 3; ++k) bc[ph][l][k] = c[k];
                 }
     }
-    for (int ph = 0; ph < 2; ++ph)
-        for (int l = 0; l < L; ++l) {
-            h->tune_ch[ph][l] = bc[ph][l][0];
-            h->tune_wpb[ph][l] = bc[ph][l][1];
-            h->tune_stg[ph][l] = bc[ph][l][2];
-        }
-    ++h->tune_gen;
-    h->prof_on = was_on;
-    drop_graphs(h);
-    return FF_OK;
+    return restore(FF_OK);                              // with bc now the fastest candidates
 }
 
 void free_ctx(ff_ctx* h);
@@ -1161,25 +1172,36 @@ ff_status serve_pump(ff_ctx* h)
     }
     for (ServeLane& l : sv->lanes) {
         if (l.busy || sv->pending.empty()) continue;
-        std::vector<ff_pair> cohort;
+        std::vector<ServeReq> taken;
         size_t bytes = 0;
-        while (!sv->pending.empty() && (int)cohort.size() < sv->max_cohort &&
+        while (!sv->pending.empty() && (int)taken.size() < sv->max_cohort &&
                bytes + sv->pending.front().bytes <= sv->lane_bytes) {
-            ServeReq r = sv->pending.front();
+            taken.push_back(sv->pending.front());
             sv->pending.pop_front();
-            FF_HIP(h, hipStreamWaitEvent(l.stream, r.ready, 0));
-            sv->ev_pool.push_back(r.ready);
+            bytes += taken.back().bytes;
+        }
+        if (taken.empty()) break;
+        // a cohort that cannot start goes back to the head of the queue, in
+        // order, with its requests' ready events: nothing submitted is lost,
+        // and a later ff_poll tries again (ff_poll reports this one's error)
+        auto requeue = [&](ff_status s, const std::string& msg) {
+            for (size_t i = taken.size(); i-- > 0;) sv->pending.push_front(taken[i]);
+            return fail(h, s, msg);
+        };
+        std::vector<ff_pair> cohort;
+        for (const ServeReq& r : taken) {
+            const hipError_t e = hipStreamWaitEvent(l.stream, r.ready, 0);
+            if (e != hipSuccess) return requeue(FF_ERR_HIP, std::string("cohort wait: ") + hipGetErrorString(e));
             cohort.push_back(r.pair);
-            l.tags.push_back(r.tag);
-            bytes += r.bytes;
         }
-        if (cohort.empty()) break;
         ff_status st = run(l.exec, cohort.data(), (int)cohort.size(), l.stream, Stop{});
-        if (st != FF_OK) {
-            l.tags.clear();
-            return fail(h, st, "cohort launch: " + l.exec->err);
+        if (st != FF_OK) return requeue(st, "cohort launch: " + l.exec->err);
+        const hipError_t e = hipEventRecord(l.done, l.stream);
+        if (e != hipSuccess) return requeue(FF_ERR_HIP, std::string("cohort completion event: ") + hipGetErrorString(e));
+        for (const ServeReq& r : taken) {
+            sv->ev_pool.push_back(r.ready);
+            l.tags.push_back(r.tag);
         }
-        FF_HIP(h, hipEventRecord(l.done, l.stream));
         l.busy = true;
     }
     return FF_OK;
@@ -1379,9 +1401,16 @@ ff_status ff_submit(ff_handle h, const ff_pair* pair, uint64_t tag, void* stream
     } else {
         FF_HIP(h, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     }
-    FF_HIP(h, hipEventRecord(ready, (hipStream_t)stream));
+    const hipError_t e = hipEventRecord(ready, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        sv->ev_pool.push_back(ready);
+        return hip_fail(h, e, "hipEventRecord(ready)");
+    }
     sv->pending.push_back(ServeReq{*pair, tag, bytes, ready});
-    return serve_pump(h);
+    // the pair is queued: a cohort that cannot start now stays queued and
+    // the next ff_poll tries again (and reports the error if it persists)
+    (void)serve_pump(h);
+    return FF_OK;
 }
 
 int32_t ff_poll(ff_handle h, uint64_t* tags_done, int32_t max)

@@ -229,3 +229,111 @@ def test_allocation_faults_return_oom_without_leaks(torch, ffm, orc, monkeypatch
     say("free device bytes before / after", free0, free1)
     assert abs(free0 - free1) < (2 << 20), (free0, free1)
     ref.close()
+
+
+def test_failed_table_upload_never_leaves_a_stale_table(torch, ffm):
+    """A batch of 17 pairs outgrows the device pair table (16 entries from
+    its first allocation).  With the table regrown but the pinned staging
+    buffer that the upload needs next refused, the call fails with
+    FF_ERR_OOM.  The next call, with the single pair whose table the handle
+    uploaded before, must upload it again into the new allocation (which
+    holds nothing yet) and give the same bits as a fresh handle."""
+    i1, i2, _ = synth.config0()
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    ref = ffm.Matcher(levels=3)
+    want = {k: v.clone() for k, v in ref.match(a, b).items()}
+    torch.cuda.synchronize()
+    m = ffm.Matcher(levels=3)
+    say("two 480x360 pairs (arena room for 17 config-0 pairs, table of 16 entries)")
+    big = [synth.translated_pair(np.random.default_rng(410 + k), 480, 360, d=(5, -3))[:2] for k in range(2)]
+    m.match_batch([(_dev(torch, x), _dev(torch, y)) for x, y in big])
+    need17 = m.workspace_bytes([(96, 128, 1)] * 17)
+    need2 = m.workspace_bytes([(360, 480, 1)] * 2)
+    assert need17 < need2, (need17, need2)             # no arena regrowth below
+    say("one config-0 pair (the table the handle then holds)")
+    out = m._outputs(96, 128)
+    m.match(a, b, out=out)
+    torch.cuda.synchronize()
+    say("17 pairs: table regrown, staging buffer refused")
+    m.fault_alloc(1)
+    with pytest.raises(ffm.FFError) as e:
+        m.match_batch([(a, b)] * 17, outs=[m._outputs(96, 128) for _ in range(17)])
+    assert e.value.status == ffm.FF_ERR_OOM
+    assert "staging" in str(e.value), str(e.value)
+    m.fault_alloc(-1)
+    say("the single pair again")
+    for t in out.values():
+        t.zero_()
+    got = m.match(a, b, out=out)
+    torch.cuda.synchronize()
+    for key in want:
+        assert torch.equal(got[key], want[key]), key
+    say("and the 17-pair batch once allocations succeed")
+    outs = m.match_batch([(a, b)] * 17)
+    torch.cuda.synchronize()
+    for o in outs:
+        for key in want:
+            assert torch.equal(o[key], want[key]), key
+    m.close()
+    ref.close()
+
+
+def test_serving_cohort_that_cannot_start_stays_queued(torch, ffm):
+    """A served pair whose cohort cannot start (its lane's first pair-table
+    allocation refused) stays queued: ff_submit succeeds, ff_poll reports
+    the error while it persists, and once allocations succeed the pair runs
+    and matches a fresh handle bit for bit."""
+    import time
+    i1, i2, _ = synth.config0()
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    ref = ffm.Matcher(levels=3)
+    want = {k: v.clone() for k, v in ref.match(a, b).items()}
+    torch.cuda.synchronize()
+    m = ffm.Matcher(levels=3)
+    m.serve_config(lanes=1, lane_bytes=4 * ref.workspace_bytes([(96, 128, 1)]))
+    say("submit with every allocation refused")
+    m.fault_alloc(0)
+    o = m.submit(a, b, tag=7)
+    assert m.inflight() == 1
+    with pytest.raises(ffm.FFError) as e:
+        m.poll()
+    assert "cohort launch" in str(e.value), str(e.value)
+    assert m.inflight() == 1
+    m.fault_alloc(-1)
+    say("poll once allocations succeed")
+    t0, got = time.time(), []
+    while not got and time.time() - t0 < 60:
+        got = m.poll()
+    assert got == [7]
+    assert m.inflight() == 0
+    for key in want:
+        assert torch.equal(o[key], want[key]), key
+    m.close()
+    ref.close()
+
+
+def test_failed_autotune_keeps_the_schedule(torch, ffm):
+    """An autotune whose first timed run cannot allocate its workspace fails
+    with FF_ERR_OOM and leaves the handle on the schedule it had; the
+    handle then still matches bit for bit."""
+    i1, i2, _ = synth.config0()
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    ref = ffm.Matcher(levels=3)
+    want = {k: v.clone() for k, v in ref.match(a, b).items()}
+    torch.cuda.synchronize()
+    m = ffm.Matcher(levels=3)
+    sched = [1, 2, 0] * 3 + [2, 4, 0] * 3
+    m.set_tuning(sched)
+    say("autotune with every allocation refused")
+    m.fault_alloc(0)
+    with pytest.raises(ffm.FFError) as e:
+        m.autotune([(a, b)])
+    assert e.value.status == ffm.FF_ERR_OOM
+    m.fault_alloc(-1)
+    assert list(m.tuning()) == sched
+    got = m.match(a, b)
+    torch.cuda.synchronize()
+    for key in want:
+        assert torch.equal(got[key], want[key]), key
+    m.close()
+    ref.close()
