@@ -302,18 +302,14 @@ __device__ __forceinline__ uint32_t luma4(const uint32_t* w, int k0)
     return out;
 }
 
-__global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
+// Luma of the 16 pixels from i0 (fewer at the plane's end): 16-byte loads
+// and one 16-byte store when the image is 16-byte aligned, else byte by byte.
+__device__ __forceinline__ void gray16(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, int C, int n,
+                                       int i0)
 {
-    const PairDev& P = pairs[blockIdx.y >> 1];
-    const int img = blockIdx.y & 1;
-    const int n = P.lv[0].W * P.lv[0].H;
-    const int i0 = (blockIdx.x * 256 + threadIdx.x) * 16;
-    if (i0 >= n) return;
-    const uint8_t* src = P.img[img];
-    uint8_t* dst = P.lv[0].gray[img];
     if (i0 + 16 <= n && ((uintptr_t)src & 15u) == 0) {
         u32x4 o;
-        if (P.C == 3) {
+        if (C == 3) {
             gcu4* s4 = (gcu4*)(src + (size_t)i0 * 3);
             const u32x4 a = s4[0], b = s4[1], c = s4[2];
             const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
@@ -326,7 +322,7 @@ __global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
     }
     for (int i = i0; i < min(i0 + 16, n); ++i) {
         uint8_t v;
-        if (P.C == 3) {
+        if (C == 3) {
             const uint8_t* p = src + (size_t)i * 3;
             v = (uint8_t)((77u * p[0] + 150u * p[1] + 29u * p[2] + 128u) >> 8);
         } else {
@@ -336,19 +332,34 @@ __global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
     }
 }
 
-// One pyramid step: 2x2 box mean rounded half up, floor dimensions.
+// grid (blocks per image, 2 * pairs): each block strides over its image's
+// 16-pixel groups (few blocks per image for batches of many small pairs).
+__global__ __launch_bounds__(256) void k_gray(const PairDev* __restrict__ pairs)
+{
+    const PairDev& P = pairs[blockIdx.y >> 1];
+    const int img = blockIdx.y & 1;
+    const int n = P.lv[0].W * P.lv[0].H;
+    const uint8_t* src = P.img[img];
+    uint8_t* dst = P.lv[0].gray[img];
+    for (int i0 = (blockIdx.x * 256 + threadIdx.x) * 16; i0 < n; i0 += gridDim.x * 256 * 16)
+        gray16(src, dst, P.C, n, i0);
+}
+
+// One pyramid step: 2x2 box mean rounded half up, floor dimensions.  grid
+// (blocks per image, 2 * pairs), each block striding over its image.
 __global__ __launch_bounds__(256) void k_down2(const PairDev* __restrict__ pairs, int level)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int img = blockIdx.y & 1;
     const LevelDev& S = P.lv[level - 1];
     const LevelDev& D = P.lv[level];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= D.W * D.H) return;
-    const int x = i % D.W, y = i / D.W;
-    const uint8_t* s = S.gray[img] + (size_t)(2 * y) * S.W + 2 * x;
-    const uint32_t sum = (uint32_t)s[0] + s[1] + s[S.W] + s[S.W + 1];
-    D.gray[img][i] = (uint8_t)((sum + 2u) >> 2);
+    const int n = D.W * D.H;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int x = i % D.W, y = i / D.W;
+        const uint8_t* s = S.gray[img] + (size_t)(2 * y) * S.W + 2 * x;
+        const uint32_t sum = (uint32_t)s[0] + s[1] + s[S.W] + s[S.W + 1];
+        D.gray[img][i] = (uint8_t)((sum + 2u) >> 2);
+    }
 }
 
 // -------------------------------------------------------- descriptors ---
@@ -596,36 +607,37 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
     const PairDev& P = pairs[blockIdx.y >> 1];
     const int img = blockIdx.y & 1;
     const LevelDev& L = P.lv[level];
-    const int N = L.W * L.H;
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n < P.nsx * P.nsy) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
-    if (n >= N) return;
-    const uint4 db = load_desc((gcu8*)L.desc[img], (size_t)(n / L.W) * L.Wp + (size_t)(n % L.W));
-    const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
-    const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
-    int nb = 0;
+    const int N = L.W * L.H, Q = P.nsx * P.nsy;                // Q <= N: seeds are pixels
+    // grid (blocks per image, 2 * pairs): each block strides over its image
+    for (int n = blockIdx.x * 256 + threadIdx.x; n < N; n += gridDim.x * 256) {
+        if (n < Q) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
+        const uint4 db = load_desc((gcu8*)L.desc[img], (size_t)(n / L.W) * L.Wp + (size_t)(n % L.W));
+        const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
+        const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+        int nb = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int v = (int)(int8_t)(bw[k >> 2] >> (8 * (k & 3)));
-        nb += v * v;
-    }
-    const int neg = -nb;                                        // in [-262144, 0]
-    const int X = -((-neg + 126) / 127);                        // floor(neg / 127), neg <= 0
-    const int rmd = neg - 127 * X;                              // 0..126
-    uint32_t beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int rem = X;
+        for (int k = 0; k < 16; ++k) {
+            const int v = (int)(int8_t)(bw[k >> 2] >> (8 * (k & 3)));
+            nb += v * v;
+        }
+        const int neg = -nb;                                        // in [-262144, 0]
+        const int X = -((-neg + 126) / 127);                        // floor(neg / 127), neg <= 0
+        const int rmd = neg - 127 * X;                              // 0..126
+        uint32_t beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int rem = X;
 #pragma unroll
-    for (int k = 0; k < 31; ++k) {
-        const int v = max(rem, -128);
-        rem -= v;
-        beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
+        for (int k = 0; k < 31; ++k) {
+            const int v = max(rem, -128);
+            rem -= v;
+            beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
+        }
+        beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
+        FF_GLOBAL u32x4* rec = (FF_GLOBAL u32x4*)(P.dbrec[img] + (size_t)n * 64);
+        rec[0] = u32x4{b.x, b.y, b.z, b.w};
+        rec[1] = u32x4{b.x, b.y, b.z, b.w};
+        rec[2] = u32x4{beta[0], beta[1], beta[2], beta[3]};
+        rec[3] = u32x4{beta[4], beta[5], beta[6], beta[7]};
     }
-    beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
-    FF_GLOBAL u32x4* rec = (FF_GLOBAL u32x4*)(P.dbrec[img] + (size_t)n * 64);
-    rec[0] = u32x4{b.x, b.y, b.z, b.w};
-    rec[1] = u32x4{b.x, b.y, b.z, b.w};
-    rec[2] = u32x4{beta[0], beta[1], beta[2], beta[3]};
-    rec[3] = u32x4{beta[4], beta[5], beta[6], beta[7]};
 }
 
 // Exact nearest neighbour of every seed of A among all coarsest pixels of B
@@ -806,51 +818,56 @@ __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict_
     const LevelDev& L = P.lv[level];
     const int W = L.W, N = L.W * L.H, Q = P.nsx * P.nsy;
     const int sub = threadIdx.x & 3;                             // tiles 4 sub .. 4 sub + 3 of the chunk
-    const int q = blockIdx.x * 64 + (threadIdx.x >> 2);          // 4 lanes per seed
-    const bool live = q < Q;
-    const unsigned long long key = live ? P.keys[dir][q] : 0ull;
-    const int S = (int)(uint32_t)(key >> 32) - (1 << 20);
-    const bool wide = (N + 15) / 16 > 65536;
-    const uint32_t tb = wide ? 0xFFFFFFFFu - (uint32_t)key : 0xFFFFu - (((uint32_t)key >> 16) & 0xFFFFu);
-    uint32_t cols = !live ? 0u : wide ? 0xFFFFu : (uint32_t)key & 0xFFFFu;
-    int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    if (live) {
-        const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
-        const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * L.Wp + sx);
-        a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
-        a3 = (int)(ad.w ^ 0x80808080u);
-    }
-    gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
-    uint32_t nmin = 0xFFFFFFFFu;
-    while (cols) {                                               // uniform within the seed's 4 lanes
-        const uint32_t j = (uint32_t)__builtin_ctz(cols);
-        cols &= cols - 1u;
-        uint4 bd[4];                                             // the lane's four tiles: loads in flight together
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
-            bd[k] = n < (uint32_t)N ? load_desc(DBd, (size_t)(n / (uint32_t)W) * L.Wp + (n % (uint32_t)W))
-                                    : make_uint4(0, 0, 0, 0);
+    // grid (blocks per image, 2 * pairs): each block strides over its
+    // pair-direction's seeds, 64 at a time (the bound is uniform per block, so
+    // every lane of a seed's group takes part in the shuffles below)
+    for (int base = blockIdx.x * 64; base < Q; base += gridDim.x * 64) {
+        const int q = base + (threadIdx.x >> 2);                 // 4 lanes per seed
+        const bool live = q < Q;
+        const unsigned long long key = live ? P.keys[dir][q] : 0ull;
+        const int S = (int)(uint32_t)(key >> 32) - (1 << 20);
+        const bool wide = (N + 15) / 16 > 65536;
+        const uint32_t tb = wide ? 0xFFFFFFFFu - (uint32_t)key : 0xFFFFu - (((uint32_t)key >> 16) & 0xFFFFu);
+        uint32_t cols = !live ? 0u : wide ? 0xFFFFu : (uint32_t)key & 0xFFFFu;
+        int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        if (live) {
+            const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
+            const uint4 ad = load_desc((gcu8*)L.desc[dir], (size_t)sy * L.Wp + sx);
+            a0 = (int)(ad.x ^ 0x80808080u), a1 = (int)(ad.y ^ 0x80808080u), a2 = (int)(ad.z ^ 0x80808080u),
+            a3 = (int)(ad.w ^ 0x80808080u);
         }
+        gcu8* __restrict__ DBd = (gcu8*)L.desc[dir ^ 1];
+        uint32_t nmin = 0xFFFFFFFFu;
+        while (cols) {                                               // uniform within the seed's 4 lanes
+            const uint32_t j = (uint32_t)__builtin_ctz(cols);
+            cols &= cols - 1u;
+            uint4 bd[4];                                             // the lane's four tiles: loads in flight together
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
-            const int b0 = (int)(bd[k].x ^ 0x80808080u), b1 = (int)(bd[k].y ^ 0x80808080u),
-                      b2 = (int)(bd[k].z ^ 0x80808080u), b3 = (int)(bd[k].w ^ 0x80808080u);
-            int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
-            ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
-            ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
-            ab = __builtin_amdgcn_sdot4(a3, b3, ab, false);
-            int bb = __builtin_amdgcn_sdot4(b0, b0, 0, false);
-            bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
-            bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
-            bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
-            if (n < (uint32_t)N && 2 * ab - bb == S) nmin = min(nmin, n);
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
+                bd[k] = n < (uint32_t)N ? load_desc(DBd, (size_t)(n / (uint32_t)W) * L.Wp + (n % (uint32_t)W))
+                                        : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t n = (tb + (uint32_t)(4 * sub + k)) * 16u + j;
+                const int b0 = (int)(bd[k].x ^ 0x80808080u), b1 = (int)(bd[k].y ^ 0x80808080u),
+                          b2 = (int)(bd[k].z ^ 0x80808080u), b3 = (int)(bd[k].w ^ 0x80808080u);
+                int ab = __builtin_amdgcn_sdot4(a0, b0, 0, false);
+                ab = __builtin_amdgcn_sdot4(a1, b1, ab, false);
+                ab = __builtin_amdgcn_sdot4(a2, b2, ab, false);
+                ab = __builtin_amdgcn_sdot4(a3, b3, ab, false);
+                int bb = __builtin_amdgcn_sdot4(b0, b0, 0, false);
+                bb = __builtin_amdgcn_sdot4(b1, b1, bb, false);
+                bb = __builtin_amdgcn_sdot4(b2, b2, bb, false);
+                bb = __builtin_amdgcn_sdot4(b3, b3, bb, false);
+                if (n < (uint32_t)N && 2 * ab - bb == S) nmin = min(nmin, n);
+            }
         }
+        nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 1, 64));
+        nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 2, 64));
+        if (live && sub == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
     }
-    nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 1, 64));
-    nmin = min(nmin, (uint32_t)__shfl_xor((int)nmin, 2, 64));
-    if (live && sub == 0) P.keys[dir][q] = (key & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - nmin);
 }
 
 // ----------------------------------------------------------- level init --
@@ -1650,14 +1667,25 @@ void noalloc_unlock(int device) { g_scratch_use[device].unlock(); }
 // ------------------------------------------------------------ launchers --
 #define FF_GRID1(n) dim3((unsigned)(((n) + 255) / 256))
 
+// Blocks per image of the per-pixel kernels (grid (blocks, 2 * pairs), each
+// block striding over its image): enough to cover the largest image in one
+// pass, but for batches of many small images at most what keeps the grid
+// near kPixelBlocks, so that blocks are not mostly started and retired.
+constexpr long long kPixelBlocks = 16384;
+unsigned blocks_per_image(long long natural, int npairs)
+{
+    const long long cap = std::max<long long>(1, kPixelBlocks / (2LL * npairs));
+    return (unsigned)std::max<long long>(1, std::min(natural, cap));
+}
 void launch_gray(const PairDev* d, int npairs, int maxpx, hipStream_t st)
 {
-    maxpx = (maxpx + 15) / 16;                                   // threads of 16 pixels
-    hipLaunchKernelGGL(k_gray, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d);
+    const long long groups = (maxpx + 15) / 16;                  // threads of 16 pixels
+    hipLaunchKernelGGL(k_gray, dim3(blocks_per_image((groups + 255) / 256, npairs), 2 * npairs), dim3(256), 0, st, d);
 }
 void launch_down2(const PairDev* d, int npairs, int level, int maxpx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_down2, dim3((maxpx + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
+    hipLaunchKernelGGL(k_down2, dim3(blocks_per_image((maxpx + 255) / 256, npairs), 2 * npairs), dim3(256), 0, st, d,
+                       level);
 }
 void launch_desc(const PairDev* d, int npairs, int level, int maxW, int maxH, hipStream_t st)
 {
@@ -1672,11 +1700,13 @@ void launch_census(const PairDev* d, int npairs, int level, int maxW, int maxH, 
 }
 void launch_seed_resolve(const PairDev* d, int npairs, int level, int stride, int maxQ, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seed_resolve, dim3((maxQ + 63) / 64, 2 * npairs), dim3(256), 0, st, d, level, stride);
+    hipLaunchKernelGGL(k_seed_resolve, dim3(blocks_per_image((maxQ + 63) / 64, npairs), 2 * npairs), dim3(256), 0, st, d,
+                       level, stride);
 }
 void launch_seed_records(const PairDev* d, int npairs, int level, int maxN, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seed_records, dim3((maxN + 255) / 256, 2 * npairs), dim3(256), 0, st, d, level);
+    hipLaunchKernelGGL(k_seed_records, dim3(blocks_per_image((maxN + 255) / 256, npairs), 2 * npairs), dim3(256), 0, st,
+                       d, level);
 }
 // Database splits: few, so that each block streams a long split and pays its
 // prologue, first chunk and epilogue rarely, yet enough to fill the GPU's

@@ -162,7 +162,9 @@ class Matcher:
         h = ctypes.c_void_p()
         st = lib().ff_create(ctypes.byref(self.params), device, ctypes.byref(h))
         if st != FF_OK:
-            raise FFError(st, "ff_create failed (device missing or not gfx950?)")
+            why = {FF_ERR_INVALID: "invalid parameters or device index", FF_ERR_UNSUPPORTED: "the device is not gfx950",
+                   FF_ERR_OOM: "pinned staging memory could not be allocated"}.get(st, "HIP error")
+            raise FFError(st, "ff_create failed: " + why)
         self._h = h
 
     # -- helpers --------------------------------------------------------
@@ -194,6 +196,12 @@ class Matcher:
         v = o.get(k)
         return ctypes.c_void_p(v.data_ptr()) if v is not None else None
 
+    # output name -> (dtype name, trailing shape after [H, W])
+    _OUT_SPEC = {"flow_f": ("int16", (2,)), "flow_b": ("int16", (2,)), "cost_f": ("int32", ()),
+                 "cost_b": ("int32", ()), "mask_f": ("uint8", ()), "mask_b": ("uint8", ()),
+                 "fberr_f": ("int32", ()), "fberr_b": ("int32", ()), "sparse_f": ("uint8", ()),
+                 "sparse_b": ("uint8", ())}
+
     def _pair(self, img1, img2, out):
         for im in (img1, img2):
             if im.dtype != self._torch.uint8 or not im.is_contiguous() or im.device != self.device:
@@ -201,6 +209,17 @@ class Matcher:
         if img1.shape != img2.shape or img1.dim() not in (2, 3):
             raise FFError(FF_ERR_INVALID, "images must share a [H, W] or [H, W, C] shape")
         H, W = int(img1.shape[0]), int(img1.shape[1])
+        # the library writes every given output in full: check each against
+        # the layout it writes before handing its pointer over
+        for k, v in out.items():
+            spec = self._OUT_SPEC.get(k)
+            if spec is None or v is None:
+                continue
+            dt, tail = spec
+            if (v.dtype != getattr(self._torch, dt) or tuple(v.shape) != (H, W) + tail or not v.is_contiguous()
+                    or v.device != self.device):
+                raise FFError(FF_ERR_INVALID, f"output {k} must be a contiguous {dt} tensor of shape "
+                                              f"{(H, W) + tail} on the handle's device")
         C = 1 if img1.dim() == 2 else int(img1.shape[2])
         p = Pair(img1.data_ptr(), img2.data_ptr(), W, H, C,
                  self._ptr(out, "flow_f"), self._ptr(out, "cost_f"), self._ptr(out, "mask_f"),

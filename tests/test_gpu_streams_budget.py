@@ -337,3 +337,30 @@ def test_failed_autotune_keeps_the_schedule(torch, ffm):
         assert torch.equal(got[key], want[key]), key
     m.close()
     ref.close()
+
+
+def test_output_tensors_are_checked_before_any_launch(torch, ffm):
+    """The binding refuses outputs whose shape, dtype, layout or device
+    differ from what the library writes (the library would write past
+    them); the handle then still matches bit for bit."""
+    i1, i2, _ = synth.config0()
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    m = ffm.Matcher(levels=3)
+    want = {k: v.clone() for k, v in m.match(a, b).items()}
+    torch.cuda.synchronize()
+    say("rejected outputs")
+    bad = [("flow_f", torch.empty((96, 127, 2), dtype=torch.int16, device="cuda")),
+           ("cost_f", torch.empty((96, 128), dtype=torch.int16, device="cuda")),
+           ("mask_b", torch.empty((128, 96), dtype=torch.uint8, device="cuda").t()),
+           ("flow_b", torch.empty((96, 128, 2), dtype=torch.int16))]
+    for k, t in bad:
+        out = m._outputs(96, 128)
+        out[k] = t
+        with pytest.raises(ffm.FFError) as e:
+            m.match(a, b, out=out)
+        assert e.value.status == ffm.FF_ERR_INVALID and k in str(e.value), (k, str(e.value))
+    got = m.match(a, b)
+    torch.cuda.synchronize()
+    for key in want:
+        assert torch.equal(got[key], want[key]), key
+    m.close()
