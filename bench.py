@@ -39,7 +39,7 @@ SCHEDULE_CENSUS = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "be367d1d1e0f6c6d", "bytes_per_launch": 1782278121}
+TRAFFIC = {"kernel_sha": "f5d34d926a0fd161", "bytes_per_launch": 1781323612}
 
 
 def kernel_sha():
