@@ -39,13 +39,21 @@ SCHEDULE_CENSUS = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "f5d34d926a0fd161", "bytes_per_launch": 1781323612}
+TRAFFIC = {"kernel_sha": "4833a0ea6cc80b7a", "bytes_per_launch": 1781323612}
 
 
 def kernel_sha():
+    """sha256[:16] of the kernels' code: ff_kernels.hip with its // comments,
+    trailing blanks and empty lines removed, so that editing a comment keeps
+    a measurement taken on the same code and any code change retires it."""
     import hashlib
     src = os.path.join(ROOT, "paper_1805_03517_amd", "csrc", "ff_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    code = []
+    for line in open(src, encoding="utf-8"):
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def level_dims(w, h, levels):

@@ -1,7 +1,9 @@
 // ff_kernels.hip -- gfx950 kernels of the Flow Fields search (FlowFields++,
 // Sec. 3.1 "Matches").  Every kernel is grouped over a batch: blockIdx.y (or
 // .z) selects the pair and the image or direction, the other grid axes cover
-// the largest level of the batch and blocks beyond a pair's own size exit.
+// the largest level of the batch and blocks beyond a pair's own size exit
+// (the per-pixel kernels cap that axis for batches of many small pairs and
+// stride over the image; the line phases of uneven batches run a work list).
 //
 // All arithmetic is integer and follows the schedule stated in include/ff.h;
 // the parallel forms used here (windowed relaxation of the scanline sweeps,
@@ -286,7 +288,8 @@ __device__ __forceinline__ void random_search(uint32_t& bf, int32_t& bc, int W, 
 // Level-0 luma of both images: Y = (77 R + 150 G + 29 B + 128) >> 8, C = 1
 // copies.  16 pixels per thread: 48 (or 16) input bytes in 16-byte loads
 // when the image is 16-byte aligned, one 16-byte store; the plane's ragged
-// end and unaligned images go byte by byte.  grid (pixels / 4096, 2 * pairs).
+// end and unaligned images go byte by byte.  grid (blocks per image, 2 * pairs),
+// each block striding over its image's 4096-pixel spans.
 __device__ __forceinline__ uint32_t luma4(const uint32_t* w, int k0)
 {
     // pixels k0 .. k0+3 of a 48-byte group held as 12 little-endian words
@@ -809,8 +812,8 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
 // Entries past the chunk's split come later than every entry of the chunk,
 // so scanning all 16 tiles finds the same first one.  The key's low word
 // becomes ~index.  4 lanes per seed, lane s taking tiles 4s .. 4s+3 of each
-// listed column in turn (64 seeds a block, so small pairs of a big batch
-// need few blocks); grid (ceil(seeds / 64), 2 * pairs), 256 threads.
+// listed column in turn, 64 seeds at a time; grid (blocks per image,
+// 2 * pairs), 256 threads, each block striding over its seeds.
 __global__ __launch_bounds__(256) void k_seed_resolve(const PairDev* __restrict__ pairs, int level, int stride)
 {
     const PairDev& P = pairs[blockIdx.y >> 1];
