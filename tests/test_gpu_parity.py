@@ -277,6 +277,40 @@ def test_seed_search_full_resolution_sampled(torch, ffm, orc, kind):
     m.close()
 
 
+@pytest.mark.parametrize("kind", ["noise", "periodic"])
+def test_seed_search_over_a_million_pixels(torch, ffm, orc, kind):
+    """Seed search over a single 1280x900 level (levels = 1: N = 1,152,000
+    pixels, 72,000 tiles of 16): past 65,536 tiles the merged key names the
+    winning chunk by its first tile alone and the resolve pass scans every
+    column of it.  Sampled seeds, the first and last ones included, against
+    the oracle's one-query search; the periodic image makes equal scores
+    cross split boundaries."""
+    W, H = 1280, 900
+    if kind == "noise":
+        i1, i2, _ = synth.translated_pair(np.random.default_rng(41), W, H, d=(7, -5))
+    else:
+        rng = np.random.default_rng(42)
+        tile = rng.integers(0, 256, size=(8, 8), dtype=np.uint8)
+        i1 = np.tile(tile, (H // 8 + 1, W // 8 + 1))[:H, :W].copy()
+        i2 = np.roll(i1, (3, 5), axis=(0, 1)).copy()
+    p = _prm(orc, levels=1)
+    m = _matcher(ffm, p)
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    D = [orc.descriptors(orc.gray(x)) for x in (i1, i2)]
+    assert (W * H + 15) // 16 > 65536
+    rng = np.random.default_rng(43)
+    for d in (0, 1):
+        say("seed search over a million pixels", kind, "dir", d, "shape", i1.shape)
+        s = m.debug_stage(a, b, ffm.STAGE_SEEDS, dir=d).cpu().numpy()
+        nsy, nsx = s.shape
+        Q = nsy * nsx
+        qs = np.unique(np.concatenate([np.arange(40), np.arange(Q - 40, Q), rng.integers(0, Q, size=80)]))
+        for q in qs:
+            y, x = (q // nsx) * 3, (q % nsx) * 3
+            assert s.reshape(-1)[q] == orc.nearest(D[d][y, x], D[1 - d]), (kind, d, int(q))
+    m.close()
+
+
 @pytest.mark.parametrize("C", [1, 3])
 def test_unaligned_buffers(torch, ffm, orc, C):
     """Images starting at odd addresses and outputs that are only 4-byte
