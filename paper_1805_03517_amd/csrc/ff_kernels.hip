@@ -954,6 +954,11 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
 // gathered at its end and selected during window w+1's first relaxation
 // round, so their memory latency overlaps other work.  The trials, their
 // order and the selection rule are those of random_search().
+// The waves of a block take their windows in lockstep (a barrier at the
+// start of each window; waves past the block's last line pass the same
+// barriers without a line): adjacent lines then gather from the same
+// neighbourhood of B at the same time and share its cache lines in L1 and
+// L2 (column phase on the 1242x375 batch: 790 -> 748 us per launch).
 template <int RC, bool COL, int CH, int CK>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
@@ -1019,6 +1024,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
 
     uint32_t carry = 0;
     for (int wi = 0; wi < nwin; ++wi) {
+        __syncthreads();                                         // windows in lockstep across the block
         const int w0 = wstart(wi);
         if (wi + 1 < nwin) load_window(wstart(wi + 1), nf0, nc0, na);
         uint32_t lp[CH], h[CH];
@@ -1180,7 +1186,10 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     // keeps its last windows in global memory between the passes.
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
-    if (!STG && !active && !xwc) return;
+    // the pipelined pass keeps the block's windows in lockstep: every wave
+    // stays to pass its barriers
+    constexpr bool PIPE = !STG && RC > 0 && CH <= 2 && CK != 2;
+    if (!PIPE && !STG && !active && !xwc) return;
     const int CS = COL ? L.Hp : L.Wp;                            // feature-plane line stride
     gcu8* __restrict__ DA = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
                             (size_t)line * CS * FB;
@@ -1234,12 +1243,14 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
         const bool lout = xwk && (COL || (fwd && upto >= 2));
         const bool quarter = CK == 2 && !COL && fwd && finit;
 
-        if constexpr (!STG && RC > 0 && CH <= 2 && CK != 2) {      // the sub-pixel refinement: generic pass
+        if constexpr (PIPE) {                                    // the sub-pixel refinement: generic pass
             if (active)
                 line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, CS, len, line, lane, fwd,
                                                      rs,
                                                  (uint32_t)level, ctr2, sc, P, dir,
                                                  (!COL && fwd && finit) ? (level == sc.levels - 1 ? 2 : 1) : 0);
+            else
+                for (int wi = 0; wi < nwin; ++wi) __syncthreads();   // the active waves' barriers, one a window
             continue;
         }
         uint32_t carry = 0;
