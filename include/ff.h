@@ -74,7 +74,8 @@ typedef enum {
 #define FF_SPARSIFY 1u      /* compute sparse_fwd / sparse_bwd (3x3-block selection) */
 #define FF_COST_CENSUS 2u   /* matching cost = Hamming distance of 7x7 Census strings
                                (Sec. 3.1) instead of descriptor SAD; seeds still
-                               match descriptors; staged schedules unsupported     */
+                               match descriptors; staged schedules (mode 1)
+                               unsupported                                         */
 #define FF_SECOND_CHECK 4u  /* two consistency checks (Sec. 3.1): the search runs a
                                second time keyed by seed2, and a match must also be
                                consistent with that search's inverse field        */
@@ -249,18 +250,21 @@ int32_t   ff_serve_inflight(ff_handle h);
 /* ---- schedule autotuning -----------------------------------------------
  * Scheduling of the propagation and random search of Sec. 3.1 only.
  * The row and column phases run one wave per image line and solve each
- * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves; with
- * `staged` = 1 the waves of a block take their windows in lockstep and read
- * random-search trials from an LDS copy of the windows' target
- * neighbourhood.  All three are scheduling choices only: the sweep's result
- * does not depend on the window, and staging changes where a descriptor is
- * read from, not which one -- no choice changes any output.  Supported
- * triples: staged 0 with chunks in {1,2,4,8} and lines in {2,4,8}; staged 1 with (chunks,
- * lines) in {(1,4), (1,8), (1,16), (2,8)}.  ff_autotune runs this batch once
+ * sweep on windows of `chunks` x 64 pixels; blocks hold `lines` waves; the
+ * mode says how the waves of a block move: 0, each at its own pace; 2, their
+ * windows in lockstep (adjacent lines then share the cache lines of B's
+ * neighbourhood); 1, in lockstep and reading random-search trials from an
+ * LDS copy of the windows' target neighbourhood.  All three are scheduling
+ * choices only: the sweep's result does not depend on the window, and
+ * lockstep and staging change when and where a descriptor is read, not
+ * which one -- no choice changes any output.  Supported triples: mode 0
+ * with chunks in {1,2,4,8} and lines in {2,4,8}; mode 2 with chunks in
+ * {1,2} and lines in {2,4,8}; mode 1 with (chunks, lines) in {(1,4), (1,8),
+ * (1,16), (2,8)} and the descriptor cost.  ff_autotune runs this batch once
  * per supported triple (twice, the second timed with events) and keeps, per
  * phase and level, the fastest; it synchronises the stream.  ff_tune_get
  * writes 6 * levels int32 (cfg[(phase * levels + level) * 3 + {0: chunks,
- * 1: lines, 2: staged}], phase 0 = row, 1 = column) and returns that count,
+ * 1: lines, 2: mode}], phase 0 = row, 1 = column) and returns that count,
  * or -1 if max is too small; ff_tune_set installs such a vector
  * (FF_ERR_INVALID for an unsupported triple).  The default is (1, 4, 0) for
  * the row phase and (1, 8, 0) for the column phase at every level.        */

@@ -954,11 +954,12 @@ __global__ __launch_bounds__(256) void k_init(const PairDev* __restrict__ pairs,
 // gathered at its end and selected during window w+1's first relaxation
 // round, so their memory latency overlaps other work.  The trials, their
 // order and the selection rule are those of random_search().
-// The waves of a block take their windows in lockstep (a barrier at the
-// start of each window; waves past the block's last line pass the same
-// barriers without a line): adjacent lines then gather from the same
-// neighbourhood of B at the same time and share its cache lines in L1 and
-// L2 (column phase on the 1242x375 batch: 790 -> 748 us per launch).
+// With `lock` (schedule mode 2) the waves of a block take their windows in
+// lockstep (a barrier at the start of each window; waves past the block's
+// last line pass the same barriers without a line): adjacent lines then
+// gather from the same neighbourhood of B at the same time and share its
+// cache lines in L1 and L2 (column phase on the 1242x375 batch: 790 -> 748
+// us per launch; on short lines the waits can cost more than that gains).
 template <int RC, bool COL, int CH, int CK>
 __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8* __restrict__ DB,
                                                     const gi2* __restrict__ Sin, int sstr, gi2* __restrict__ S,
@@ -966,7 +967,8 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
                                                     int line,
                                                     int lane,
                                                     bool fwd, bool rs, uint32_t level, uint32_t ctr2,
-                                                    const SearchConst& sc, const PairDev& P, int dir, int initc)
+                                                    const SearchConst& sc, const PairDev& P, int dir, int initc,
+                                                    bool lock)
 {
     using FT = typename Feat<CK>::T;
     constexpr int WIN = 64 * CH;
@@ -1024,7 +1026,7 @@ __device__ __forceinline__ void line_pass_pipelined(gcu8* __restrict__ DA, gcu8*
 
     uint32_t carry = 0;
     for (int wi = 0; wi < nwin; ++wi) {
-        __syncthreads();                                         // windows in lockstep across the block
+        if (lock) __syncthreads();                               // windows in lockstep across the block
         const int w0 = wstart(wi);
         if (wi + 1 < nwin) load_window(wstart(wi + 1), nf0, nc0, na);
         uint32_t lp[CH], h[CH];
@@ -1144,7 +1146,7 @@ struct StageDims {
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restrict__ pairs, int level,
                                                          int iter, int upto, SearchConst sc, int xw, int finit,
-                                                         const uint32_t* __restrict__ items)
+                                                         const uint32_t* __restrict__ items, int lock)
 {
     static_assert(!STG || CK == 0, "the staged random search holds descriptors");
     const uint32_t rlev = sc.rng_level >= 0 ? (uint32_t)sc.rng_level : (uint32_t)level;   // Philox level word
@@ -1186,10 +1188,11 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
     // keeps its last windows in global memory between the passes.
     const bool xwk = xw != 0;
     const bool xwc = COL && xwk;                                 // block-wide copies: every wave takes part
-    // the pipelined pass keeps the block's windows in lockstep: every wave
-    // stays to pass its barriers
+    // the pipelined pass with lock keeps the block's windows in lockstep:
+    // every wave stays to pass its barriers
     constexpr bool PIPE = !STG && RC > 0 && CH <= 2 && CK != 2;
-    if (!PIPE && !STG && !active && !xwc) return;
+    const bool lk = PIPE && lock != 0;
+    if (!lk && !STG && !active && !xwc) return;
     const int CS = COL ? L.Hp : L.Wp;                            // feature-plane line stride
     gcu8* __restrict__ DA = (gcu8*)(CK == 1 ? (COL ? L.cenT[dir] : L.cen[dir]) : (COL ? L.descT[dir] : L.desc[dir])) +
                             (size_t)line * CS * FB;
@@ -1248,8 +1251,8 @@ __global__ __launch_bounds__(64 * WPB) void k_line_phase(const PairDev* __restri
                 line_pass_pipelined<RC, COL, CH, CK>(DA, DB, Sin, sstr, S, lin, lout, lline, W, H, CS, len, line, lane, fwd,
                                                      rs,
                                                  (uint32_t)level, ctr2, sc, P, dir,
-                                                 (!COL && fwd && finit) ? (level == sc.levels - 1 ? 2 : 1) : 0);
-            else
+                                                 (!COL && fwd && finit) ? (level == sc.levels - 1 ? 2 : 1) : 0, lk);
+            else if (lk)
                 for (int wi = 0; wi < nwin; ++wi) __syncthreads();   // the active waves' barriers, one a window
             continue;
         }
@@ -1782,22 +1785,25 @@ int row_lds_pixels(int maxlen)
 
 template <int RC, bool COL, int CH, int WPB, bool STG, int CK>
 void launch_line_t(const PairDev* d, int npairs, int level, int iter, int upto, const SearchConst& sc, int nlines,
-                   int maxlen, int finit, const LineWork& wk, hipStream_t st)
+                   int maxlen, int finit, const LineWork& wk, int lock, hipStream_t st)
 {
     const int xw = !line_cross_write(WPB, maxlen) ? 0 : COL ? maxlen : row_lds_pixels<CH, WPB>(maxlen);
     const size_t dyn = (size_t)WPB * xw * kLdsBytesPerPx;
     const dim3 grid = wk.items ? dim3((unsigned)wk.n) : dim3((nlines + WPB - 1) / WPB, 2 * npairs);
     hipLaunchKernelGGL((k_line_phase<RC, COL, CH, WPB, STG, CK>), grid, dim3(64 * WPB), dyn, st, d, level, iter, upto,
-                       sc, xw, finit, wk.items);
+                       sc, xw, finit, wk.items, lock);
 }
 
 template <int RC, bool COL, int CK>
 bool launch_line_rc(int ch, int wpb, int stg, const PairDev* d, int npairs, int level, int iter, int upto,
                     const SearchConst& sc, int nlines, int maxlen, int finit, const LineWork& wk, hipStream_t st)
 {
+    // stg: 0 free-running, 1 staged (lockstep, LDS neighbourhood), 2 lockstep
+    // (the pipelined pass's windows; the other passes run free)
 #define FF_LINE_CASE(C, B, G)                                                                        \
-    if (ch == C && wpb == B && stg == G) {                                                           \
-        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, st); \
+    if (ch == C && wpb == B && (stg == G || (G == 0 && stg == 2))) {                                 \
+        launch_line_t<RC, COL, C, B, G != 0, CK>(d, npairs, level, iter, upto, sc, nlines, maxlen, finit, wk, \
+                                                 stg == 2 ? 1 : 0, st);                              \
         return true;                                                                                 \
     }
     if constexpr (CK == 2) {                                     // the refinement's fixed schedule
@@ -1876,7 +1882,7 @@ bool launch_line_phase(bool col, int ch, int wpb, int stg, int ck, const PairDev
 // Whether the row phase with this schedule can take over the level init.
 bool line_fused_init(int ch, int stg, const SearchConst& sc)
 {
-    return sc.radius == 16 && stg == 0 && ch <= 2;
+    return sc.radius == 16 && stg != 1 && ch <= 2;
 }
 void launch_transpose_state(const PairDev* d, int npairs, int level, int to_t, int maxW, int maxH, hipStream_t st)
 {

@@ -128,7 +128,7 @@ struct ff_ctx {
     // search (set by ff_autotune / ff_tune_set)
     int tune_ch[2][kMaxLevels] = {{1, 1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1, 1}};
     int tune_wpb[2][kMaxLevels] = {{4, 4, 4, 4, 4, 4, 4, 4}, {8, 8, 8, 8, 8, 8, 8, 8}};
-    int tune_stg[2][kMaxLevels] = {};          // 1 = random search reads a staged LDS neighbourhood
+    int tune_stg[2][kMaxLevels] = {};          // mode: 0 free-running, 1 staged LDS neighbourhood, 2 lockstep windows
 };
 
 // Serving: continuous batching over `lanes` concurrent cohorts.  Each lane
@@ -942,6 +942,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
 {
     static const int kCand[][3] = {{1, 2, 0}, {1, 4, 0}, {1, 8, 0}, {2, 2, 0}, {2, 4, 0}, {2, 8, 0},
                                    {4, 2, 0}, {4, 4, 0}, {4, 8, 0}, {8, 2, 0}, {8, 4, 0}, {8, 8, 0},
+                                   {1, 2, 2}, {1, 4, 2}, {1, 8, 2}, {2, 2, 2}, {2, 4, 2}, {2, 8, 2},
                                    {1, 4, 1}, {1, 8, 1}, {1, 16, 1}, {2, 8, 1}};
     const int L = h->prm.levels;
     double best[2][kMaxLevels];
@@ -972,7 +973,7 @@ ff_status autotune(ff_ctx* h, const ff_pair* pairs, int n, hipStream_t st)
     std::vector<Timed> discard;
     (void)collect_profile(h, discard);
     for (const auto& c : kCand) {
-        if (c[2] && (h->prm.flags & FF_COST_CENSUS)) continue;   // staged: descriptor cost only
+        if (c[2] == 1 && (h->prm.flags & FF_COST_CENSUS)) continue;   // staged: descriptor cost only
         drop_graphs(h);
         ++h->tune_gen;
         for (int ph = 0; ph < 2; ++ph)
@@ -1354,7 +1355,8 @@ ff_status ff_tune_set(ff_handle h, const int32_t* cfg, int32_t n)
         const int ch = cfg[i], wpb = cfg[i + 1], stg = cfg[i + 2];
         const bool plain = stg == 0 && (ch == 1 || ch == 2 || ch == 4 || ch == 8) && (wpb == 2 || wpb == 4 || wpb == 8);
         const bool staged = stg == 1 && ((ch == 1 && (wpb == 4 || wpb == 8 || wpb == 16)) || (ch == 2 && wpb == 8));
-        if (!plain && !staged) return fail(h, FF_ERR_INVALID, "unsupported (chunks, lines, staged) triple");
+        const bool lockstep = stg == 2 && (ch == 1 || ch == 2) && (wpb == 2 || wpb == 4 || wpb == 8);
+        if (!plain && !staged && !lockstep) return fail(h, FF_ERR_INVALID, "unsupported (chunks, lines, mode) triple");
         if (staged && (h->prm.flags & FF_COST_CENSUS))
             return fail(h, FF_ERR_INVALID, "staged schedules need the descriptor cost");
     }

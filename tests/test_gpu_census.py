@@ -163,7 +163,7 @@ def test_census_schedules_and_rejections(torch, ffm, orc):
     assert e.value.status == ffm.FF_ERR_INVALID
     a, b = torch.from_numpy(i1).cuda(), torch.from_numpy(i2).cuda()
     m.autotune([(a, b)] * 4)
-    assert all(v == 0 for v in m.tuning()[2::3])
+    assert all(v in (0, 2) for v in m.tuning()[2::3])        # free-running or lockstep, never staged
     got = m.match(a, b)
     torch.cuda.synchronize()
     _compare(orc.match(i1, i2, p), got, "census after autotune")

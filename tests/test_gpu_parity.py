@@ -502,9 +502,10 @@ def test_schedule_tuning_never_changes_output(torch, ffm, orc):
     _compare_outputs(r0, ref[1], "default schedule vs oracle")
     say("autotune")
     cfg = m.autotune(dev)
-    assert len(cfg) == 24 and all(cfg[i + 2] in (0, 1) for i in range(0, 24, 3))
+    assert len(cfg) == 24 and all(cfg[i + 2] in (0, 1, 2) for i in range(0, 24, 3))
     trials = [cfg, [2, 2, 0] * 8, [8, 8, 0] * 8, [2, 8, 0, 8, 2, 0] * 4, [1, 8, 1] * 8, [1, 16, 1] * 8,
-              [1, 4, 1] * 8, [2, 8, 1] * 8, [1, 8, 1, 4, 4, 0] * 4, [1, 2, 0] * 8, [1, 8, 0, 2, 4, 0] * 4]
+              [1, 4, 1] * 8, [2, 8, 1] * 8, [1, 8, 1, 4, 4, 0] * 4, [1, 2, 0] * 8, [1, 8, 0, 2, 4, 0] * 4,
+              [1, 8, 2] * 8, [2, 2, 2] * 8, [1, 4, 2, 1, 8, 1] * 4, [2, 8, 2, 4, 4, 0] * 4]
     for trial in trials:
         say("schedule", trial)
         m.set_tuning(trial)
@@ -517,6 +518,8 @@ def test_schedule_tuning_never_changes_output(torch, ffm, orc):
         m.set_tuning([3, 3, 0] * 8)
     with pytest.raises(ffm.FFError):
         m.set_tuning([4, 4, 1] * 8)          # staging is not built for 256-px windows
+    with pytest.raises(ffm.FFError):
+        m.set_tuning([4, 4, 2] * 8)          # lockstep is a mode of the pipelined pass (1-2 chunks)
     m.close()
 
 

@@ -72,11 +72,24 @@ def _schedule(name, L):
     if name is None:
         return None
     return {"generic": [4, 4, 0] * L + [4, 4, 0] * L, "pipelined": [1, 8, 0] * L + [2, 4, 0] * L,
-            "narrow": [1, 2, 0] * L + [2, 2, 0] * L, "staged": [1, 8, 1] * L + [2, 8, 1] * L}[name]
+            "narrow": [1, 2, 0] * L + [2, 2, 0] * L, "staged": [1, 8, 1] * L + [2, 8, 1] * L,
+            "lockstep": [1, 4, 2] * L + [1, 8, 2] * L, "lockstep_mixed": [2, 2, 2, 1, 8, 0] * L}[name]
 
 
 @pytest.mark.parametrize("c", CASES, ids=[f"case{k}" for k in range(len(CASES))])
 def test_random_configuration(torch, ffm, orc, c):
+    _run_case(torch, ffm, orc, c)
+
+
+@pytest.mark.parametrize("c", CASES[:24], ids=[f"case{k}" for k in range(24)])
+def test_random_configuration_lockstep(torch, ffm, orc, c):
+    """The first 24 configurations again with the line phases' windows in
+    lockstep (schedule mode 2; mixed with free-running levels in every
+    other case): still bit-exact."""
+    _run_case(torch, ffm, orc, dict(c, sched="lockstep" if c["img_seed"] % 2 == 0 else "lockstep_mixed"))
+
+
+def _run_case(torch, ffm, orc, c):
     i1, i2 = _images(c)
     seed2 = 0xC0DE if c["second"] else None
     kw = dict(levels=c["levels"], seed_stride=c["stride"], iters=c["iters"], rs_radius=c["R"], fb_eps=c["eps"],
