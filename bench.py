@@ -28,7 +28,8 @@ W0, H0, LEVELS = 1242, 375, 4
 HBM_PEAK_GBS = 8000.0
 
 # Line-kernel schedule for this workload as picked by ff_autotune on MI355X:
-# (chunks per window, lines per block, staged) for row levels 0..3, then col
+# (chunks per window, lines per block, mode: 0 free-running, 1 staged, 2 lockstep)
+# for row levels 0..3, then col
 # levels 0..3.  Any schedule gives identical outputs; --autotune re-tunes.
 SCHEDULE_C1 = [1, 4, 2, 1, 4, 0, 1, 2, 0, 1, 8, 0, 1, 8, 2, 1, 8, 2, 1, 4, 0, 1, 4, 0]
 # The same for the Census cost on the Sintel-shaped batch (used by the
