@@ -34,13 +34,13 @@ HBM_PEAK_GBS = 8000.0
 SCHEDULE_C1 = [1, 4, 2, 1, 4, 0, 1, 2, 0, 1, 8, 0, 1, 8, 2, 1, 8, 2, 1, 4, 0, 1, 4, 0]
 # The same for the Census cost on the Sintel-shaped batch (used by the
 # profiler legs, which do not autotune).
-SCHEDULE_CENSUS = [1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 4, 0, 1, 8, 0, 1, 8, 0, 1, 4, 0, 1, 4, 0]
+SCHEDULE_CENSUS = [1, 4, 2, 1, 4, 0, 1, 2, 0, 1, 4, 0, 1, 8, 2, 1, 8, 0, 1, 4, 0, 1, 4, 0]
 
 # HBM traffic of the col-phase kernel per launch (average over the 8
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "4833a0ea6cc80b7a", "bytes_per_launch": 1781323612}
+TRAFFIC = {"kernel_sha": "1656e7497b822a26", "bytes_per_launch": 1689469109}
 
 
 def kernel_sha():
