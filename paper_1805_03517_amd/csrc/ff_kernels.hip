@@ -1558,12 +1558,19 @@ __global__ __launch_bounds__(256) void k_fb2(const PairDev* __restrict__ pairs, 
 
 // ----------------------------------------------------- sparsification --
 // Sec. 3.1 (minimum matches s from Table 3): the level-0 image is cut into
-// 3x3 blocks from the origin, partial at the right and bottom borders.  One
-// thread per block counts its consistent matches (error <= eps^2) and, with
-// at least s of them, keeps the lowest error -- a row-major scan with a
-// strict '<' keeps the lowest y*W + x among equals; all nine keep bytes of
-// the block are written.  Lanes take consecutive blocks of a block row, so
-// their reads and writes are contiguous.  grid (ceil(W/3)/256, ceil(H/3), 2 * pairs)
+// 3x3 blocks from the origin, partial at the right and bottom borders.  A
+// block with at least s consistent matches (error <= eps^2) keeps the one of
+// lowest error, the lowest y*W + x among equals; all nine keep bytes of the
+// block are written.  A wave covers kSparseBands bands of 3 rows over 63
+// columns (21 blocks per band; lane 63 idle): each lane reads and writes its
+// own column, so every load and store instruction touches 63 consecutive
+// pixels of a row, and all the wave's loads are in flight together.  Per
+// band a lane folds its column into a count and the smallest key (error << 4
+// | 3 dy + dx; error <= eps^2 <= 2^24, so the key fits), and the block's
+// three lanes combine theirs with shuffles.
+// grid (ceil(ceil(W/63)/4), ceil(H/(3 kSparseBands)), 2 * pairs)
+constexpr int kSparseBands = 4;
+
 __global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pairs, int eps2, int s)
 {
     const PairDev& P = pairs[blockIdx.z >> 1];
@@ -1572,35 +1579,36 @@ __global__ __launch_bounds__(256) void k_sparse(const PairDev* __restrict__ pair
     if (!keep) return;                                           // output not requested
     const LevelDev& L = P.lv[0];
     const int W = L.W, H = L.H;
-    const int x0 = 3 * (blockIdx.x * 256 + threadIdx.x), y0 = 3 * blockIdx.y;
-    if (x0 >= W || y0 >= H) return;
+    const int lane = threadIdx.x & 63;
+    const int x0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * 63, y0 = 3 * kSparseBands * blockIdx.y;
+    if (x0 >= W || y0 >= H) return;                              // uniform per wave
+    const int x = x0 + lane, dx = lane % 3, lead = lane - dx;     // lead: the block's first lane
+    const bool col = lane < 63 && x < W;
     const FF_GLOBAL int32_t* err = (const FF_GLOBAL int32_t*)P.fberr[dir];
-    int count = 0, best = -1;
-    int32_t be = 0;
+    int32_t e[3 * kSparseBands];
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
+    for (int r = 0; r < 3 * kSparseBands; ++r)
+        e[r] = col && y0 + r < H ? err[(uint32_t)(y0 + r) * (uint32_t)W + (uint32_t)x] : kInf;
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const int x = x0 + dx, y = y0 + dy;
-            if (x >= W || y >= H) continue;
-            const int32_t e = err[(uint32_t)y * (uint32_t)W + (uint32_t)x];
-            if (e <= eps2) {
+    for (int band = 0; band < kSparseBands; ++band) {
+        const int yb = y0 + 3 * band;
+        if (yb >= H) break;                                      // uniform
+        int count = 0;
+        uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+            if (e[3 * band + dy] <= eps2) {
                 ++count;
-                if (best < 0 || e < be) {
-                    be = e;
-                    best = 3 * dy + dx;
-                }
+                key = min(key, ((uint32_t)e[3 * band + dy] << 4) | (uint32_t)(3 * dy + dx));
             }
-        }
-    }
-    if (count < s) best = -1;
+        const int total = __shfl(count, lead, 64) + __shfl(count, lead + 1, 64) + __shfl(count, lead + 2, 64);
+        const uint32_t kb = min(min((uint32_t)__shfl((int)key, lead, 64), (uint32_t)__shfl((int)key, lead + 1, 64)),
+                                (uint32_t)__shfl((int)key, lead + 2, 64));
+        const int best = total >= s && kb != 0xFFFFFFFFu ? (int)(kb & 15u) : -1;
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const int x = x0 + dx, y = y0 + dy;
-            if (x < W && y < H) keep[(uint32_t)y * (uint32_t)W + (uint32_t)x] = (3 * dy + dx == best) ? 1 : 0;
-        }
+        for (int dy = 0; dy < 3; ++dy)
+            if (col && yb + dy < H)
+                keep[(uint32_t)(yb + dy) * (uint32_t)W + (uint32_t)x] = 3 * dy + dx == best ? 1 : 0;
     }
 }
 
@@ -1908,8 +1916,8 @@ void launch_fb2(const PairDev* d, int npairs, int eps2, int shift, int maxpx, hi
 }
 void launch_sparse(const PairDev* d, int npairs, int eps2, int s, int maxW, int maxH, hipStream_t st)
 {
-    const int nbx = (maxW + 2) / 3, nby = (maxH + 2) / 3;
-    hipLaunchKernelGGL(k_sparse, dim3((nbx + 255) / 256, nby, 2 * npairs), dim3(256), 0, st, d, eps2, s);
+    const int waves = (maxW + 62) / 63, nby = (maxH + 3 * kSparseBands - 1) / (3 * kSparseBands);
+    hipLaunchKernelGGL(k_sparse, dim3((waves + 3) / 4, nby, 2 * npairs), dim3(256), 0, st, d, eps2, s);
 }
 void launch_copy_desc_signed(const uint8_t* src, int8_t* dst, int W, int H, int Wp, hipStream_t st)
 {
