@@ -611,35 +611,50 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
     const int img = blockIdx.y & 1;
     const LevelDev& L = P.lv[level];
     const int N = L.W * L.H, Q = P.nsx * P.nsy;                // Q <= N: seeds are pixels
+    // a thread builds one record in LDS; the block then stores its 256
+    // records (16 KiB) as consecutive 16-byte pieces, so every store
+    // instruction writes 1 KiB of consecutive memory
+    __shared__ u32x4 recs[256 * 4];
+    FF_GLOBAL u32x4* out = (FF_GLOBAL u32x4*)P.dbrec[img];
     // grid (blocks per image, 2 * pairs): each block strides over its image
-    for (int n = blockIdx.x * 256 + threadIdx.x; n < N; n += gridDim.x * 256) {
-        if (n < Q) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
-        const uint4 db = load_desc((gcu8*)L.desc[img], (size_t)(n / L.W) * L.Wp + (size_t)(n % L.W));
-        const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
-        const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
-        int nb = 0;
+    for (int base = blockIdx.x * 256; base < N; base += gridDim.x * 256) {   // uniform per block
+        const int n = base + (int)threadIdx.x;
+        if (n < N) {
+            if (n < Q) ((FF_GLOBAL unsigned long long*)P.keys[img])[n] = 0ull;
+            const uint4 db = load_desc((gcu8*)L.desc[img], (size_t)(n / L.W) * L.Wp + (size_t)(n % L.W));
+            const uint4 b = make_uint4(db.x ^ 0x80808080u, db.y ^ 0x80808080u, db.z ^ 0x80808080u, db.w ^ 0x80808080u);
+            const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+            int nb = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int v = (int)(int8_t)(bw[k >> 2] >> (8 * (k & 3)));
-            nb += v * v;
-        }
-        const int neg = -nb;                                        // in [-262144, 0]
-        const int X = -((-neg + 126) / 127);                        // floor(neg / 127), neg <= 0
-        const int rmd = neg - 127 * X;                              // 0..126
-        uint32_t beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int rem = X;
+            for (int k = 0; k < 16; ++k) {
+                const int v = (int)(int8_t)(bw[k >> 2] >> (8 * (k & 3)));
+                nb += v * v;
+            }
+            const int neg = -nb;                                    // in [-262144, 0]
+            const int X = -((-neg + 126) / 127);                    // floor(neg / 127), neg <= 0
+            const int rmd = neg - 127 * X;                          // 0..126
+            uint32_t beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int rem = X;
 #pragma unroll
-        for (int k = 0; k < 31; ++k) {
-            const int v = max(rem, -128);
-            rem -= v;
-            beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
+            for (int k = 0; k < 31; ++k) {
+                const int v = max(rem, -128);
+                rem -= v;
+                beta[k >> 2] |= (uint32_t)(v & 0xFF) << (8 * (k & 3));
+            }
+            beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
+            recs[threadIdx.x * 4 + 0] = u32x4{b.x, b.y, b.z, b.w};
+            recs[threadIdx.x * 4 + 1] = u32x4{b.x, b.y, b.z, b.w};
+            recs[threadIdx.x * 4 + 2] = u32x4{beta[0], beta[1], beta[2], beta[3]};
+            recs[threadIdx.x * 4 + 3] = u32x4{beta[4], beta[5], beta[6], beta[7]};
         }
-        beta[7] |= (uint32_t)(rmd & 0xFF) << 24;
-        FF_GLOBAL u32x4* rec = (FF_GLOBAL u32x4*)(P.dbrec[img] + (size_t)n * 64);
-        rec[0] = u32x4{b.x, b.y, b.z, b.w};
-        rec[1] = u32x4{b.x, b.y, b.z, b.w};
-        rec[2] = u32x4{beta[0], beta[1], beta[2], beta[3]};
-        rec[3] = u32x4{beta[4], beta[5], beta[6], beta[7]};
+        __syncthreads();
+        const int pieces = min(256, N - base) * 4;                 // 16-byte pieces of this block's records
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = (int)threadIdx.x + 256 * k;
+            if (e < pieces) out[(size_t)base * 4 + (size_t)e] = recs[e];
+        }
+        __syncthreads();                                          // records stored before the next round overwrites them
     }
 }
 
