@@ -67,6 +67,25 @@ def _run_pair(torch, ffm, orc, i1, i2, p, tag, schedule=None):
 
 
 # ------------------------------------------------------ stage parity ----
+@pytest.mark.parametrize("W,H,L", [(131, 67, 4), (1242, 375, 4), (64, 32, 4), (65, 33, 2), (200, 130, 6),
+                                   (300, 257, 8), (97, 45, 3)])
+def test_pyramid_levels(torch, ffm, orc, W, H, L):
+    """Every pyramid level against the oracle, up to 8 levels: odd sizes
+    whose floor dimensions drop a source row or column, sizes that are
+    multiples of the block and a full 1242 x 375 frame."""
+    rng = np.random.default_rng(W * 7 + H)
+    i1, i2, _ = synth.translated_pair(rng, W, H, d=(3, -2), rect=(min(16, W // 2), min(12, H // 2)), rect_d=(2, 1))
+    m = _matcher(ffm, _prm(orc, levels=L))
+    a, b = _dev(torch, i1), _dev(torch, i2)
+    for img, x in ((0, i1), (1, i2)):
+        pyr = orc.pyramid(orc.gray(x), L)
+        for l in range(L):
+            say("pyramid", W, H, "levels", L, "image", img, "level", l)
+            g = m.debug_stage(a, b, ffm.STAGE_PYRAMID, image=img, level=l).cpu().numpy()
+            assert np.array_equal(g, pyr[l]), (W, H, L, img, l)
+    m.close()
+
+
 @pytest.mark.parametrize("schedule", ["default", "generic"])
 def test_stage_parity_config0(torch, ffm, orc, schedule):
     """Every intermediate against the oracle: with the default schedule
