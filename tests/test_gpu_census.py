@@ -113,7 +113,7 @@ EDGE = [
 ]
 
 
-@pytest.mark.parametrize("sched", ["default", "pipelined", "wide"])
+@pytest.mark.parametrize("sched", ["default", "pipelined", "wide", "lockstep", "lockstep_mixed"])
 @pytest.mark.parametrize("case", EDGE, ids=[f"{c[0]}x{c[1]}c{c[2]}L{c[3]}" for c in EDGE])
 def test_census_edge_shapes(torch, ffm, orc, case, sched):
     W, H, C, L, st, R, eps, T = case
@@ -126,7 +126,10 @@ def test_census_edge_shapes(torch, ffm, orc, case, sched):
         i1 = np.stack([c[0] for c in ch], -1)
         i2 = np.stack([c[1] for c in ch], -1)
     p = _prm(orc, levels=L, seed_stride=st, iters=T, rs_radius=R, fb_eps=eps)
-    schedule = {"default": None, "pipelined": [1, 8, 0] * L + [2, 4, 0] * L, "wide": [8, 2, 0] * L + [4, 8, 0] * L}[sched]
+    # lockstep: a block's lines take their windows together (mode 2), alone or
+    # mixed with free-running levels
+    schedule = {"default": None, "pipelined": [1, 8, 0] * L + [2, 4, 0] * L, "wide": [8, 2, 0] * L + [4, 8, 0] * L,
+                "lockstep": [1, 4, 2] * L + [1, 8, 2] * L, "lockstep_mixed": [2, 2, 2, 1, 8, 0] * L}[sched]
     _run(torch, ffm, orc, i1, i2, p, f"census edge {case}", schedule=schedule)
 
 
