@@ -675,6 +675,18 @@ __global__ __launch_bounds__(256) void k_seed_records(const PairDev* __restrict_
 // chunk; splits merge (score, chunk) per seed and k_seed_resolve picks the
 // lowest index inside the winning chunk -- the lowest index wins every tie.
 // grid (ceil(seed tiles / (4 MQ)), splits, 2 * pairs), 256 threads.
+// Largest value over the 16 lanes of each row of the wave: DPP within the
+// row -- two quad swaps, then rotations of the row by 4 and by 8 lanes (every
+// source lane lies in the row, so no lane reads the bound value).
+__device__ __forceinline__ int row16_max(int k)
+{
+    k = max(k, __builtin_amdgcn_mov_dpp(k, 0xB1, 0xF, 0xF, true));    // quad_perm [1, 0, 3, 2]
+    k = max(k, __builtin_amdgcn_mov_dpp(k, 0x4E, 0xF, 0xF, true));    // quad_perm [2, 3, 0, 1]
+    k = max(k, __builtin_amdgcn_mov_dpp(k, 0x124, 0xF, 0xF, true));   // row_ror:4
+    k = max(k, __builtin_amdgcn_mov_dpp(k, 0x128, 0xF, 0xF, true));   // row_ror:8
+    return k;
+}
+
 constexpr int kSeedChunk = 16;                                   // tiles (16 KiB) per LDS chunk
 constexpr int kNoScore = -(1 << 20);                             // below every score; << 11 gives INT32_MIN
 
@@ -701,6 +713,9 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
     const int m = lane & 15, g = lane >> 4;
     __shared__ v4i tiles[kSeedChunk * 64];
 
+    // a seed's grid cell (q % nsx, q / nsx) from one division per wave: q =
+    // y0 nsx + r0 + 16 mq + m, and the lane takes whole rows off its offset
+    const int nsx = P.nsx, y0 = qbase / nsx, r0 = qbase - y0 * nsx;
     v4i A[MQ];
 #pragma unroll
     for (int mq = 0; mq < MQ; ++mq) {
@@ -708,7 +723,12 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
         if (g >= 2) {
             A[mq] = v4i{0x7F7F7F7F, 0x7F7F7F7F, 0x7F7F7F7F, g == 2 ? 0x7F7F7F7F : 0x017F7F7F};
         } else if (q < Q) {
-            const int sx = (q % P.nsx) * stride, sy = (q / P.nsx) * stride;
+            int cx = r0 + 16 * mq + m, cy = y0;
+            while (cx >= nsx) {
+                cx -= nsx;
+                ++cy;
+            }
+            const int sx = cx * stride, sy = cy * stride;
             const uint4 d = load_desc((gcu8*)L.desc[dir], (size_t)sy * L.Wp + sx);
             A[mq] = v4i{(int)(d.x ^ 0x80808080u), (int)(d.y ^ 0x80808080u), (int)(d.z ^ 0x80808080u),
                         (int)(d.w ^ 0x80808080u)};
@@ -747,12 +767,26 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
         auto score = [&](auto LIVE) {
             constexpr int LV = decltype(LIVE)::value;
             const int tfull = min(tb + nt, N >> 4);
+            // the first two full tiles start the running maxima
             int cm[LV][4];
-#pragma unroll
-            for (int mq = 0; mq < LV; ++mq)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) cm[mq][i] = kNoScore;
             int t = tb;
+            if (t + 1 < tfull) {
+                const v4i B0 = T[(uint32_t)lane];
+                const v4i B1 = T[64u + (uint32_t)lane];
+#pragma unroll
+                for (int mq = 0; mq < LV; ++mq) {
+                    const v4i acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B0, zero, 0, 0, 0);
+                    const v4i acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mq], B1, zero, 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cm[mq][i] = max(acc0[i], acc1[i]);
+                }
+                t += 2;
+            } else {
+#pragma unroll
+                for (int mq = 0; mq < LV; ++mq)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cm[mq][i] = kNoScore;
+            }
             for (; t + 1 < tfull; t += 2) {
                 const v4i B0 = T[(uint32_t)(t - tb) * 64u + (uint32_t)lane];
                 const v4i B1 = T[(uint32_t)(t - tb) * 64u + 64u + (uint32_t)lane];
@@ -803,9 +837,7 @@ __global__ __launch_bounds__(256) void k_seed_nn(const PairDev* __restrict__ pai
         if (mq >= live) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int k = best[mq][i];
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) k = max(k, __shfl_xor(k, off, 64));
+            const int k = row16_max(best[mq][i]);
             const uint32_t cols = (uint32_t)(__ballot(best[mq][i] == k) >> (16 * g)) & 0xFFFFu;
             const int q = qbase + 16 * mq + 4 * g + i;
             if (m == 0 && q < Q && (k >> 11) != kNoScore) {
