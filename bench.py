@@ -40,7 +40,7 @@ SCHEDULE_CENSUS = [1, 4, 2, 1, 4, 0, 1, 2, 0, 1, 4, 0, 1, 8, 2, 1, 8, 0, 1, 4, 0
 # launches of a step), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this benchmark scaled by the copy calibration (x2.0 fetch, x1.0 write).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"kernel_sha": "2b86f20dd745b23d", "bytes_per_launch": 1688971061}
+TRAFFIC = {"kernel_sha": "fc99365dee475289", "bytes_per_launch": 1689564396}
 
 
 def kernel_sha():
