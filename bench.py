@@ -43,12 +43,13 @@ SCHEDULE_CENSUS = [1, 4, 2, 1, 4, 0, 1, 2, 0, 1, 4, 0, 1, 8, 2, 1, 8, 0, 1, 4, 0
 TRAFFIC = {"kernel_sha": "fc99365dee475289", "bytes_per_launch": 1689564396}
 
 
-def kernel_sha():
-    """sha256[:16] of the kernels' code: ff_kernels.hip with its // comments,
-    trailing blanks and empty lines removed, so that editing a comment keeps
-    a measurement taken on the same code and any code change retires it."""
+def kernel_sha(src=None):
+    """sha256[:16] of the kernels' code: ff_kernels.hip (or the file `src`)
+    with its // comments, trailing blanks and empty lines removed, so that
+    editing a comment keeps a measurement taken on the same code and any code
+    change retires it."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1805_03517_amd", "csrc", "ff_kernels.hip")
+    src = src or os.path.join(ROOT, "paper_1805_03517_amd", "csrc", "ff_kernels.hip")
     code = []
     for line in open(src, encoding="utf-8"):
         line = line.split("//", 1)[0].rstrip()

@@ -1,7 +1,7 @@
 """bench.py's arithmetic and contract paths that need no GPU: level sizes and
 seed counts, the algorithmic byte model (every candidate gather of the
-schedule counted once), the per-kernel roofline table, and the one-GPU
-message for --gpus > 1."""
+schedule counted once), the per-kernel roofline table, the kernel-code hash
+that gates the traffic figure, and the one-GPU message for --gpus > 1."""
 import os
 import subprocess
 import sys
@@ -50,6 +50,21 @@ def test_kernel_rooflines_from_a_profile():
         w * h for w, h in bench.level_dims(bench.W0, bench.H0, bench.LEVELS)) * 2 * batch
     assert col["frac"] == pytest.approx(col["achieved"] / bench.HBM_PEAK_GBS)
     assert col["achieved"] == pytest.approx(col["bytes_per_step"] / 4e-3 / 1e9)
+
+
+def test_kernel_hash_ignores_comments_and_follows_code(tmp_path):
+    """The traffic figure is reported only for the kernel code it was
+    measured on: comment and blank-line edits keep the hash, code edits
+    change it."""
+    a = tmp_path / "a.hip"
+    a.write_text("int f(int x)\n{\n    return x + 1;   // one more\n}\n")
+    b = tmp_path / "b.hip"
+    b.write_text("// a header comment\nint f(int x)\n{\n\n    return x + 1;   // a different note\n}\n")
+    c = tmp_path / "c.hip"
+    c.write_text("int f(int x)\n{\n    return x + 2;   // one more\n}\n")
+    assert bench.kernel_sha(str(a)) == bench.kernel_sha(str(b))
+    assert bench.kernel_sha(str(a)) != bench.kernel_sha(str(c))
+    assert len(bench.kernel_sha()) == 16
 
 
 def test_more_than_one_gpu_exits_with_a_message():
